@@ -1,0 +1,300 @@
+// capi.cpp -- the exported C ABI (declared in include/mplu.h): argument checks, workspace
+// layout and the host-side loops of the blocked LU (Kouya Sec. 3, Fig. 8) and of the
+// forward / backward substitutions (Sec. 4).  All work is enqueued on the caller's
+// stream; nothing here allocates, frees or synchronises.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/mplu.h"
+#include "common.hpp"
+
+using namespace mplu;
+
+namespace {
+
+constexpr int kDefaultPanel = 64;
+constexpr int kMaxPanel = 128;
+constexpr int kSolveBlock = 64;
+
+inline bool prec_ok(int p) { return p == 2 || p == 3 || p == 4; }
+
+// 0 if the matrix descriptor is usable for rows x cols
+inline bool mat_ok(const mplu_zmat_t &A, int64_t rows, int64_t cols) {
+  if (rows < 0 || cols < 0) return false;
+  if (rows == 0 || cols == 0) return true;
+  if (A.planes == nullptr) return false;
+  if (A.ld < (rows > 1 ? rows : 1)) return false;
+  if (A.plane_stride < A.ld * cols) return false;
+  return true;
+}
+
+inline ZM zm(const mplu_zmat_t &A) { return ZM{A.planes, A.ld, A.plane_stride}; }
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline int panel_width(const mplu_opts_t *o) {
+  int kb = (o && o->panel > 0) ? o->panel : kDefaultPanel;
+  return kb > kMaxPanel ? kMaxPanel : kb;
+}
+
+inline int gemm_method(const mplu_opts_t *o) { return o ? o->gemm : MPLU_GEMM_3M; }
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    if ((x) != hipSuccess) return MPLU_E_HIP; \
+  } while (0)
+
+int getrs_ws(int C, int64_t n, int64_t nrhs, size_t *bytes) {
+  *bytes = align256(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)) +
+           align256(sizeof(double) * 2 * C * (size_t)(n > 0 ? n : 1) * (size_t)(nrhs > 0 ? nrhs : 1));
+  return 0;
+}
+
+int getrf_ws(int C, int64_t m, int64_t n, const mplu_opts_t *o, size_t *bytes) {
+  const int64_t mn = m < n ? m : n;
+  int kb = panel_width(o);
+  if (mn > 0 && kb > mn) kb = (int)mn;
+  if (kb < 1) kb = 1;
+  *bytes = panel_ws_bytes(C, kb);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mplu_version(void) { return 10000; }
+
+const char *mplu_strerror(int code) {
+  switch (code) {
+    case MPLU_OK: return "success";
+    case MPLU_E_WORKSPACE: return "workspace too small";
+    case MPLU_E_HIP: return "HIP runtime error or kernel launch failure";
+    case MPLU_E_UNSUPPORTED: return "unsupported size or option combination";
+    default: break;
+  }
+  if (code < 0 && code > -20) return "invalid argument";
+  return "unknown error";
+}
+
+int mplu_zrenorm(int prec, int64_t m, int64_t n, mplu_zmat_t A, void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!mat_ok(A, m, n)) return -4;
+  HIPCHK(launch_renorm(prec, m, n, zm(A), (hipStream_t)stream));
+  return 0;
+}
+
+int mplu_zconvert(int prec_src, int prec_dst, int64_t m, int64_t n, mplu_zmat_t A,
+                  mplu_zmat_t B, void *stream) {
+  if (!prec_ok(prec_src)) return -1;
+  if (!prec_ok(prec_dst)) return -2;
+  if (m < 0) return -3;
+  if (n < 0) return -4;
+  if (!mat_ok(A, m, n)) return -5;
+  if (!mat_ok(B, m, n)) return -6;
+  HIPCHK(launch_convert(prec_src, prec_dst, m, n, zm(A), zm(B), (hipStream_t)stream));
+  return 0;
+}
+
+int mplu_zgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
+                        size_t *bytes) {
+  if (!prec_ok(prec)) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!bytes) return -5;
+  return getrf_ws(prec, m, n, opts, bytes);
+}
+
+int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
+                int32_t *d_info, const mplu_opts_t *opts, void *d_work, size_t work_bytes,
+                void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!mat_ok(A, m, n)) return -4;
+  const int64_t mn = m < n ? m : n;
+  if (mn > 0 && d_ipiv == nullptr) return -5;
+  if (d_info == nullptr) return -6;
+  if (opts && (opts->panel < 0 || opts->flags != 0)) return -7;
+  const int method = gemm_method(opts);
+  if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M && method != MPLU_GEMM_SPLIT_F64 &&
+      method != MPLU_GEMM_SPLIT_I8)
+    return -7;
+  if (method == MPLU_GEMM_SPLIT_F64 || method == MPLU_GEMM_SPLIT_I8) return MPLU_E_UNSUPPORTED;
+  size_t need = 0;
+  getrf_ws(prec, m, n, opts, &need);
+  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
+  if (work_bytes < need) return MPLU_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = prec;
+  int kb = panel_width(opts);
+  if (mn > 0 && kb > mn) kb = (int)mn;
+  // the panel must fit its grid of co-resident workgroups
+  for (int64_t j = 0; j < mn; j += kb) {
+    const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
+    if (panel_geometry(C, m - j, jb).G == 0) return MPLU_E_UNSUPPORTED;
+  }
+  HIPCHK(launch_fill_i32(d_info, 0, 1, s));
+  const ZM a = zm(A);
+  for (int64_t j = 0; j < mn; j += kb) {
+    const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
+    HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, d_work, s));
+    HIPCHK(launch_laswp(C, a, j, j + jb, n, d_work, jb, s));
+    if (j + jb < n) {
+      HIPCHK(launch_trsm(C, true, true, false, a, j, jb, a, j, j + jb, n - j - jb, s));
+      if (j + jb < m)
+        HIPCHK(launch_gemm(C, method == MPLU_GEMM_3M ? 1 : 0, 'N', 'N', m - j - jb, n - j - jb,
+                           jb, -1, a, j + jb, j, a, j, j + jb, 1, a, j + jb, j + jb, s));
+    }
+  }
+  return 0;
+}
+
+int mplu_zgetrs_wsbytes(int prec, int64_t n, int64_t nrhs, size_t *bytes) {
+  if (!prec_ok(prec)) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (!bytes) return -4;
+  return getrs_ws(prec, n, nrhs, bytes);
+}
+
+int mplu_zgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_zmat_t LU,
+                const int32_t *d_ipiv, mplu_zmat_t B, void *d_work, size_t work_bytes,
+                void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (trans != 'N' && trans != 'C') return -2;
+  if (n < 0) return -3;
+  if (nrhs < 0) return -4;
+  if (!mat_ok(LU, n, n)) return -5;
+  if (n > 0 && d_ipiv == nullptr) return -6;
+  if (!mat_ok(B, n, nrhs)) return -7;
+  size_t need = 0;
+  getrs_ws(prec, n, nrhs, &need);
+  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
+  if (work_bytes < need) return MPLU_E_WORKSPACE;
+  if (n == 0 || nrhs == 0) return 0;
+  if (n > 40960) return MPLU_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  const int C = prec;
+  int32_t *perm = (int32_t *)d_work;
+  double *wbuf = (double *)((char *)d_work + align256(sizeof(int32_t) * (size_t)n));
+  const ZM w{wbuf, n, n * nrhs};
+  const ZM lu = zm(LU), b = zm(B);
+  HIPCHK(launch_perm(d_ipiv, n, perm, s));
+  const int NB = kSolveBlock;
+  const int64_t nblk = (n + NB - 1) / NB;
+  if (trans == 'N') {
+    HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, false, s));
+    for (int64_t bi = 0; bi < nblk; ++bi) {  // L y = P b
+      const int64_t i0 = bi * NB;
+      const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
+      HIPCHK(launch_trsm(C, true, true, false, lu, i0, nb, w, i0, 0, nrhs, s));
+      if (i0 + nb < n)
+        HIPCHK(launch_gemm(C, 0, 'N', 'N', n - i0 - nb, nrhs, nb, -1, lu, i0 + nb, i0, w, i0, 0,
+                           1, w, i0 + nb, 0, s));
+    }
+    for (int64_t bi = nblk - 1; bi >= 0; --bi) {  // U x = y
+      const int64_t i0 = bi * NB;
+      const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
+      HIPCHK(launch_trsm(C, false, false, false, lu, i0, nb, w, i0, 0, nrhs, s));
+      if (i0 > 0)
+        HIPCHK(launch_gemm(C, 0, 'N', 'N', i0, nrhs, nb, -1, lu, 0, i0, w, i0, 0, 1, w, 0, 0, s));
+    }
+    // W holds x in natural order: identity copy back
+    HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, true, s));
+  } else {
+    HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, false, s));
+    for (int64_t bi = 0; bi < nblk; ++bi) {  // U^H z = b
+      const int64_t i0 = bi * NB;
+      const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
+      HIPCHK(launch_trsm(C, false, false, true, lu, i0, nb, w, i0, 0, nrhs, s));
+      if (i0 + nb < n)
+        HIPCHK(launch_gemm(C, 0, 'C', 'N', n - i0 - nb, nrhs, nb, -1, lu, i0, i0 + nb, w, i0, 0,
+                           1, w, i0 + nb, 0, s));
+    }
+    for (int64_t bi = nblk - 1; bi >= 0; --bi) {  // L^H w = z
+      const int64_t i0 = bi * NB;
+      const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
+      HIPCHK(launch_trsm(C, true, true, true, lu, i0, nb, w, i0, 0, nrhs, s));
+      if (i0 > 0)
+        HIPCHK(launch_gemm(C, 0, 'C', 'N', i0, nrhs, nb, -1, lu, i0, 0, w, i0, 0, 1, w, 0, 0, s));
+    }
+    HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, true, s));  // x = P^T w
+  }
+  return 0;
+}
+
+int mplu_zgesv_wsbytes(int prec, int64_t n, int64_t nrhs, const mplu_opts_t *opts,
+                       size_t *bytes) {
+  if (!prec_ok(prec)) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (!bytes) return -5;
+  size_t a = 0, b = 0;
+  getrf_ws(prec, n, n, opts, &a);
+  getrs_ws(prec, n, nrhs, &b);
+  *bytes = a > b ? a : b;
+  return 0;
+}
+
+int mplu_zgesv(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv,
+               mplu_zmat_t B, int32_t *d_info, const mplu_opts_t *opts, void *d_work,
+               size_t work_bytes, void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (!mat_ok(A, n, n)) return -4;
+  if (n > 0 && d_ipiv == nullptr) return -5;
+  if (!mat_ok(B, n, nrhs)) return -6;
+  if (d_info == nullptr) return -7;
+  size_t need = 0;
+  mplu_zgesv_wsbytes(prec, n, nrhs, opts, &need);
+  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -9;
+  if (work_bytes < need) return MPLU_E_WORKSPACE;
+  int rc = mplu_zgetrf(prec, n, n, A, d_ipiv, d_info, opts, d_work, work_bytes, stream);
+  if (rc == -7) return -8;  // the options (the only argument not checked above)
+  if (rc != 0) return rc;
+  return mplu_zgetrs(prec, 'N', n, nrhs, A, d_ipiv, B, d_work, work_bytes, stream);
+}
+
+int mplu_zgemm_wsbytes(int prec, int64_t m, int64_t n, int64_t k, int method,
+                       const mplu_opts_t *opts, size_t *bytes) {
+  (void)opts;
+  if (!prec_ok(prec)) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (k < 0) return -4;
+  if (method < 0 || method > 3) return -5;
+  if (!bytes) return -7;
+  *bytes = 0;
+  return 0;
+}
+
+int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, int alpha_sign,
+               mplu_zmat_t A, mplu_zmat_t B, int beta, mplu_zmat_t Cm, int method,
+               const mplu_opts_t *opts, void *d_work, size_t work_bytes, void *stream) {
+  (void)opts;
+  (void)d_work;
+  (void)work_bytes;
+  if (!prec_ok(prec)) return -1;
+  if (opA != 'N' && opA != 'T' && opA != 'C') return -2;
+  if (opB != 'N' && opB != 'T' && opB != 'C') return -3;
+  if (m < 0) return -4;
+  if (n < 0) return -5;
+  if (k < 0) return -6;
+  if (alpha_sign != 1 && alpha_sign != -1) return -7;
+  if (!mat_ok(A, opA == 'N' ? m : k, opA == 'N' ? k : m)) return -8;
+  if (!mat_ok(B, opB == 'N' ? k : n, opB == 'N' ? n : k)) return -9;
+  if (beta != 0 && beta != 1) return -10;
+  if (!mat_ok(Cm, m, n)) return -11;
+  if (method < 0 || method > 3) return -12;
+  if (method >= 2) return MPLU_E_UNSUPPORTED;
+  HIPCHK(launch_gemm(prec, method == MPLU_GEMM_3M ? 1 : 0, opA, opB, m, n, k, alpha_sign, zm(A),
+                     0, 0, zm(B), 0, 0, beta, zm(Cm), 0, 0, (hipStream_t)stream));
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// common.hpp -- matrix descriptors, plane access and launcher declarations shared by the
+// HIP kernels of the library.
+//
+// Storage (Kouya Sec. 2.2, Fig. 1): real and imaginary parts are kept apart; each part is
+// C binary64 component planes.  Plane q = ri*C + c sits at p + q*ps; within a plane the
+// matrix is column-major with leading dimension ld.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mp.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mplu {
+
+struct ZM {
+  double *p;
+  int64_t ld;
+  int64_t ps;
+};
+
+template <int C>
+__device__ __forceinline__ void ld_z(const ZM &A, int64_t i, int64_t j, double (&re)[C],
+                                     double (&im)[C]) {
+  const double *b = A.p + j * A.ld + i;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    re[c] = b[(int64_t)c * A.ps];
+    im[c] = b[(int64_t)(C + c) * A.ps];
+  }
+}
+
+template <int C>
+__device__ __forceinline__ void st_z(const ZM &A, int64_t i, int64_t j, const double (&re)[C],
+                                     const double (&im)[C]) {
+  double *b = A.p + j * A.ld + i;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    b[(int64_t)c * A.ps] = re[c];
+    b[(int64_t)(C + c) * A.ps] = im[c];
+  }
+}
+
+// ------------------------------------------------------------------ launcher interface
+// Every launcher validates nothing (the C ABI does) and returns the launch status.
+
+hipError_t launch_renorm(int C, int64_t m, int64_t n, ZM A, hipStream_t s);
+hipError_t launch_convert(int Cs, int Cd, int64_t m, int64_t n, ZM A, ZM B, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
+
+struct PanelGeom {
+  int G;  // workgroups
+  int R;  // rows per workgroup
+  size_t lds;
+};
+// choose the panel grid for mp rows and kb columns; G == 0 if it cannot fit
+PanelGeom panel_geometry(int C, int64_t mp, int kb);
+size_t panel_ws_bytes(int C, int kb);
+
+// factor rows [j, m) x columns [j, j+kb) in place; writes ipiv[j..j+kb), info, and the
+// swap list for the other columns into the workspace
+hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
+                        int32_t *info, void *ws, hipStream_t s);
+// apply the swap list left by launch_panel to columns [0, c0) and [c1, n)
+hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
+                        int kb, hipStream_t s);
+
+// op(T) X = X for an nb x nb triangle T of matrix Tm at (t0, t0), X = rows [x0, x0+nb) x
+// cols [c0, c0+ncols) of Xm.  lower: T stored lower; unit: unit diagonal; conj: op = ^H
+hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
+                       ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s);
+
+// Cm := beta Cm + alpha op(A) op(B);  method 0 = 4M, 1 = 3M
+hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,
+                       int alpha_sign, ZM A, int64_t ai, int64_t aj, ZM B, int64_t bi,
+                       int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s);
+
+// getrs helpers: perm from ipiv (n entries), then gather / scatter rows of B
+hipError_t launch_perm(const int32_t *ipiv, int64_t n, int32_t *perm, hipStream_t s);
+hipError_t launch_gather_rows(int C, const int32_t *perm, int64_t n, int64_t nrhs, ZM B, ZM W,
+                              bool scatter, hipStream_t s);
+
+}  // namespace mplu

@@ -1,0 +1,164 @@
+// k_elem.hip -- element-wise kernels: canonicalisation of stored components, precision
+// conversion, integer fill, and the row permutation used by the solves.
+#include "common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mplu {
+
+template <int C>
+__global__ __launch_bounds__(256) void k_renorm(int64_t m, int64_t n, ZM A) {
+  const int64_t total = m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % m, j = e / m;
+    double re[C], im[C], o[C];
+    ld_z<C>(A, i, j, re, im);
+    mp::renorm<C>(re, o);
+    mp::copy<C>(o, re);
+    mp::renorm<C>(im, o);
+    st_z<C>(A, i, j, re, o);
+  }
+}
+
+// Cs -> Cd components.  Widening copies and zero-pads (exact).  Narrowing renormalises,
+// then folds the dropped tail into the last kept component.
+template <int Cs, int Cd>
+__global__ __launch_bounds__(256) void k_convert(int64_t m, int64_t n, ZM A, ZM B) {
+  const int64_t total = m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % m, j = e / m;
+    double re[Cs], im[Cs];
+    ld_z<Cs>(A, i, j, re, im);
+    double part[2][Cs];
+    mp::renorm<Cs>(re, part[0]);
+    mp::renorm<Cs>(im, part[1]);
+    double o[2][Cd];
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+#pragma unroll
+      for (int c = 0; c < Cd; ++c) o[ri][c] = c < Cs ? part[ri][c] : 0.0;
+      if (Cd < Cs) {
+        double tail = 0.0;
+#pragma unroll
+        for (int c = Cs - 1; c >= Cd; --c) tail += part[ri][c];
+        o[ri][Cd - 1] += tail;
+      }
+    }
+    st_z<Cd>(B, i, j, o[0], o[1]);
+  }
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+// perm[k] = original row that ends up at row k after the interchanges of ipiv, applied in
+// order (one workgroup: the row index array lives in LDS while the swaps are replayed).
+__global__ __launch_bounds__(1024) void k_perm(const int32_t *ipiv, int64_t n, int32_t *perm) {
+  extern __shared__ int32_t sp[];
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) sp[i] = (int32_t)i;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int64_t k = 0; k < n; ++k) {
+      const int32_t p = ipiv[k] - 1;
+      if (p != k && p >= 0 && p < n) {
+        const int32_t t = sp[k];
+        sp[k] = sp[p];
+        sp[p] = t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) perm[i] = sp[i];
+}
+
+// gather: W[k, :] = B[perm[k], :];  scatter: B[perm[k], :] = W[k, :]
+template <int C>
+__global__ __launch_bounds__(256) void k_gather(const int32_t *perm, int64_t n, int64_t nrhs,
+                                                ZM B, ZM W, int scatter) {
+  const int64_t total = n * nrhs * 2 * C;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e % n;
+    const int64_t rest = e / n;
+    const int64_t r = rest % nrhs;
+    const int64_t q = rest / nrhs;
+    const int64_t src = perm ? perm[k] : k;
+    double *bp = B.p + q * B.ps + r * B.ld + src;
+    double *wp = W.p + q * W.ps + r * W.ld + k;
+    if (scatter) *bp = *wp;
+    else *wp = *bp;
+  }
+}
+
+static inline int grid_for(int64_t total, int threads) {
+  int64_t g = (total + threads - 1) / threads;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_renorm(int C, int64_t m, int64_t n, ZM A, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int g = grid_for(m * n, 256);
+  switch (C) {
+    case 2: hipLaunchKernelGGL(k_renorm<2>, dim3(g), dim3(256), 0, s, m, n, A); break;
+    case 3: hipLaunchKernelGGL(k_renorm<3>, dim3(g), dim3(256), 0, s, m, n, A); break;
+    case 4: hipLaunchKernelGGL(k_renorm<4>, dim3(g), dim3(256), 0, s, m, n, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define CONV_CASE(a, b)                                                               \
+  if (Cs == a && Cd == b) {                                                           \
+    hipLaunchKernelGGL((k_convert<a, b>), dim3(g), dim3(256), 0, s, m, n, A, B);      \
+    return hipGetLastError();                                                         \
+  }
+
+hipError_t launch_convert(int Cs, int Cd, int64_t m, int64_t n, ZM A, ZM B, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int g = grid_for(m * n, 256);
+  CONV_CASE(2, 2) CONV_CASE(2, 3) CONV_CASE(2, 4)
+  CONV_CASE(3, 2) CONV_CASE(3, 3) CONV_CASE(3, 4)
+  CONV_CASE(4, 2) CONV_CASE(4, 3) CONV_CASE(4, 4)
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, 256)), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_perm(const int32_t *ipiv, int64_t n, int32_t *perm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds = sizeof(int32_t) * (size_t)n;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_perm,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_perm, dim3(1), dim3(1024), lds, s, ipiv, n, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int C, const int32_t *perm, int64_t n, int64_t nrhs, ZM B, ZM W,
+                              bool scatter, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  const int g = grid_for(n * nrhs * 2 * C, 256);
+  switch (C) {
+    case 2: hipLaunchKernelGGL(k_gather<2>, dim3(g), dim3(256), 0, s, perm, n, nrhs, B, W, (int)scatter); break;
+    case 3: hipLaunchKernelGGL(k_gather<3>, dim3(g), dim3(256), 0, s, perm, n, nrhs, B, W, (int)scatter); break;
+    case 4: hipLaunchKernelGGL(k_gather<4>, dim3(g), dim3(256), 0, s, perm, n, nrhs, B, W, (int)scatter); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mplu

@@ -1,0 +1,239 @@
+// k_gemm.hip -- complex multi-component matrix product
+//     Cm := beta*Cm + alpha * op(A) * op(B)
+// by the 4M method (Kouya Eq. 4m) or the 3M method (Eq. 3m_cemm).  This is the trailing
+// update A22 -= L21 U12 of the blocked LU (Sec. 3), where nearly all the time goes.
+//
+// Design for gfx950: the product is bound by FP64 vector arithmetic (each complex MAC is
+// 36 (3M, DD) to ~350 (3M, QD) FP64 instructions), so the kernel is a classic LDS-tiled
+// register-blocked GEMM: a workgroup owns a BM x BN output tile, stages BK-deep slabs of
+// op(A) and op(B) in LDS (for 3M together with the rounded sums Re+Im of Eq. 3m_cemm,
+// computed once per staged element), and each thread accumulates a TM x TN micro-tile in
+// level accumulators (see mp.hpp).  3M keeps T1 = ReA ReB, T2 = ImA ImB and
+// T3 = (ReA+ImA)(ReB+ImB) apart over the whole K range and combines them in the
+// epilogue: Re = T1 - T2, Im = T3 - T1 - T2, added to Cm with a single rounding per part.
+// 4M accumulates straight into Cm's value (alpha folded into the staged A).
+#include "common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mplu {
+
+struct GemmArgs {
+  ZM A, B, Cm;
+  int64_t ai, aj, bi, bj, ci, cj;
+  int64_t m, n, k;
+  int opA, opB;  // 'N', 'T', 'C'
+  int alpha, beta;
+};
+
+template <int C, bool M3, int BM, int BN, int BK, int TM, int TN>
+__global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
+  constexpr int NT = (BM / TM) * (BN / TN);
+  constexpr int NV = M3 ? 3 : 2;
+  constexpr int SX = BN / TN;  // threads along n
+  constexpr int SY = BM / TM;  // threads along m
+  __shared__ double sA[BK][NV][C][BM];
+  __shared__ double sB[BK][NV][C][BN];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % SX, ty = tid / SX;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+
+  // accumulators
+  double acc[NV][TM][TN][C];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[v][i][jj][c] = 0.0;
+
+  if (!M3 && g.beta) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < TN; ++jj) {
+        const int64_t mi = m0 + ty + i * SY, nj = n0 + tx + jj * SX;
+        if (mi < g.m && nj < g.n) {
+          double re[C], im[C];
+          ld_z<C>(g.Cm, g.ci + mi, g.cj + nj, re, im);
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            acc[0][i][jj][c] = re[c];
+            acc[1][i][jj][c] = im[c];
+          }
+        }
+      }
+  }
+
+  const double asign = (!M3 && g.alpha < 0) ? -1.0 : 1.0;
+
+  for (int64_t k0 = 0; k0 < g.k; k0 += BK) {
+    // stage op(A)[m0 .. m0+BM) x [k0 .. k0+BK)
+    for (int e = tid; e < BM * BK; e += NT) {
+      int mm, kk;
+      if (g.opA == 'N') { mm = e % BM; kk = e / BM; }
+      else { kk = e % BK; mm = e / BK; }
+      const int64_t gi = m0 + mm, gt = k0 + kk;
+      double re[C], im[C];
+      if (gi < g.m && gt < g.k) {
+        if (g.opA == 'N') ld_z<C>(g.A, g.ai + gi, g.aj + gt, re, im);
+        else ld_z<C>(g.A, g.ai + gt, g.aj + gi, re, im);
+        const double isg = (g.opA == 'C') ? -asign : asign;
+#pragma unroll
+        for (int c = 0; c < C; ++c) { re[c] *= asign; im[c] *= isg; }
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) { re[c] = 0.0; im[c] = 0.0; }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) { sA[kk][0][c][mm] = re[c]; sA[kk][1][c][mm] = im[c]; }
+      if (M3) {
+        double s[C];
+        mp::add<C>(re, im, s);
+#pragma unroll
+        for (int c = 0; c < C; ++c) sA[kk][NV - 1][c][mm] = s[c];
+      }
+    }
+    // stage op(B)[k0 .. k0+BK) x [n0 .. n0+BN)
+    for (int e = tid; e < BN * BK; e += NT) {
+      int nn, kk;
+      if (g.opB == 'N') { kk = e % BK; nn = e / BK; }
+      else { nn = e % BN; kk = e / BN; }
+      const int64_t gj = n0 + nn, gt = k0 + kk;
+      double re[C], im[C];
+      if (gj < g.n && gt < g.k) {
+        if (g.opB == 'N') ld_z<C>(g.B, g.bi + gt, g.bj + gj, re, im);
+        else ld_z<C>(g.B, g.bi + gj, g.bj + gt, re, im);
+        if (g.opB == 'C') {
+#pragma unroll
+          for (int c = 0; c < C; ++c) im[c] = -im[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) { re[c] = 0.0; im[c] = 0.0; }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) { sB[kk][0][c][nn] = re[c]; sB[kk][1][c][nn] = im[c]; }
+      if (M3) {
+        double s[C];
+        mp::add<C>(re, im, s);
+#pragma unroll
+        for (int c = 0; c < C; ++c) sB[kk][NV - 1][c][nn] = s[c];
+      }
+    }
+    __syncthreads();
+
+#pragma unroll 1
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[NV][TM][C], b[NV][TN][C];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int c = 0; c < C; ++c) a[v][i][c] = sA[kk][v][c][ty + i * SY];
+#pragma unroll
+        for (int jj = 0; jj < TN; ++jj)
+#pragma unroll
+          for (int c = 0; c < C; ++c) b[v][jj][c] = sB[kk][v][c][tx + jj * SX];
+      }
+      if (M3) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int jj = 0; jj < TN; ++jj) {
+            mp::mac<C>(acc[0][i][jj], a[0][i], b[0][jj]);
+            mp::mac<C>(acc[1][i][jj], a[1][i], b[1][jj]);
+            mp::mac<C>(acc[NV - 1][i][jj], a[NV - 1][i], b[NV - 1][jj]);
+          }
+      } else {
+        double na[TM][C];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int c = 0; c < C; ++c) na[i][c] = -a[1][i][c];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int jj = 0; jj < TN; ++jj) {
+            mp::mac<C>(acc[0][i][jj], a[0][i], b[0][jj]);
+            mp::mac<C>(acc[0][i][jj], na[i], b[1][jj]);
+            mp::mac<C>(acc[1][i][jj], a[0][i], b[1][jj]);
+            mp::mac<C>(acc[1][i][jj], a[1][i], b[0][jj]);
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < TN; ++jj) {
+      const int64_t mi = m0 + ty + i * SY, nj = n0 + tx + jj * SX;
+      if (mi >= g.m || nj >= g.n) continue;
+      double ore[C], oim[C];
+      if (M3) {
+        double t1[C], t2[C], t3[C];
+        mp::renorm<C>(acc[0][i][jj], t1);
+        mp::renorm<C>(acc[1][i][jj], t2);
+        mp::renorm<C>(acc[NV - 1][i][jj], t3);
+        if (g.alpha < 0) {
+          mp::neg<C>(t1, t1);
+          mp::neg<C>(t2, t2);
+          mp::neg<C>(t3, t3);
+        }
+        double lr[C], li[C];
+        if (g.beta) {
+          ld_z<C>(g.Cm, g.ci + mi, g.cj + nj, lr, li);
+        } else {
+          mp::set_zero<C>(lr);
+          mp::set_zero<C>(li);
+        }
+        mp::push_mp<C>(lr, t1);
+        mp::push_mp_neg<C>(lr, t2);
+        mp::push_mp<C>(li, t3);
+        mp::push_mp_neg<C>(li, t1);
+        mp::push_mp_neg<C>(li, t2);
+        mp::renorm<C>(lr, ore);
+        mp::renorm<C>(li, oim);
+      } else {
+        mp::renorm<C>(acc[0][i][jj], ore);
+        mp::renorm<C>(acc[1][i][jj], oim);
+      }
+      st_z<C>(g.Cm, g.ci + mi, g.cj + nj, ore, oim);
+    }
+}
+
+template <int C, bool M3, int BM, int BN, int BK, int TM, int TN>
+static hipError_t go(const GemmArgs &a, hipStream_t s) {
+  constexpr int NT = (BM / TM) * (BN / TN);
+  const dim3 grid((unsigned)((a.n + BN - 1) / BN), (unsigned)((a.m + BM - 1) / BM));
+  hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN>), grid, dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,
+                       int alpha_sign, ZM A, int64_t ai, int64_t aj, ZM B, int64_t bi,
+                       int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  GemmArgs a;
+  a.A = A; a.B = B; a.Cm = Cm;
+  a.ai = ai; a.aj = aj; a.bi = bi; a.bj = bj; a.ci = ci; a.cj = cj;
+  a.m = m; a.n = n; a.k = k;
+  a.opA = opA; a.opB = opB;
+  a.alpha = alpha_sign; a.beta = beta;
+  const bool m3 = (method == 1);
+  switch (C) {
+    case 2: return m3 ? go<2, true, 32, 32, 8, 2, 2>(a, s) : go<2, false, 32, 32, 8, 2, 2>(a, s);
+    case 3: return m3 ? go<3, true, 32, 32, 8, 2, 2>(a, s) : go<3, false, 32, 32, 8, 2, 2>(a, s);
+    case 4: return m3 ? go<4, true, 32, 32, 8, 2, 2>(a, s) : go<4, false, 32, 32, 8, 2, 2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mplu

@@ -1,0 +1,514 @@
+// k_panel.hip -- panel factorisation with partial pivoting and the row interchanges it
+// implies for the rest of the matrix (Kouya Sec. 3: LU with partial pivoting, blocked
+// with panel width K; LAPACK getf2 semantics for the panel).
+//
+// Design for gfx950: the panel (rows j..m-1, columns j..j+kb-1) is split by rows over G
+// co-resident workgroups; each keeps its rows of the panel in LDS for the whole panel.
+// Each column costs one grid-wide barrier: before it, every workgroup publishes its local
+// pivot candidate (value, row, and the candidate row itself) and the owner of row k
+// publishes row k; after it, every workgroup reduces the G candidates to the same winner
+// (ties -> lowest row), performs its part of the interchange from the published rows,
+// scales its part of the column by the pivot's reciprocal and applies the rank-1 update
+// to its rows.  Nothing else touches global memory until the panel is written back.
+#include <limits.h>
+
+#include "common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mplu {
+
+static constexpr int PNT = 256;        // threads per panel workgroup
+static constexpr int PGMAX = 256;      // max workgroups (one partial per thread)
+static constexpr int PKBMAX = 128;     // max panel width
+static constexpr size_t PLDS_BUDGET = 160 * 1024;
+static constexpr unsigned SPIN_LIMIT = 1u << 25;  // ~2 s of s_sleep before giving up
+
+// ------------------------------------------------------------------ workspace layout
+// [0, 256)              barrier words: count, generation, timeout flag
+// part  : 2 x PGMAX x (C+1) doubles  (cabs1 components, row index)
+// cand  : 2 x PGMAX x 2C x kb doubles
+// rowk  : 2 x 2C x kb doubles
+// swl   : 1 + 2 x (2 kb) int32  (count, dst rows, src rows)
+struct PanelWS {
+  unsigned *bar;
+  double *part, *cand, *rowk;
+  int32_t *swl;
+};
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static inline PanelWS carve(void *ws, int C, int kb, size_t *total) {
+  char *b = (char *)ws;
+  size_t off = 256;
+  PanelWS w;
+  w.bar = (unsigned *)b;
+  w.part = (double *)(b + off);
+  off = align256(off + sizeof(double) * 2 * PGMAX * (C + 1));
+  w.cand = (double *)(b + off);
+  off = align256(off + sizeof(double) * 2 * PGMAX * 2 * C * kb);
+  w.rowk = (double *)(b + off);
+  off = align256(off + sizeof(double) * 2 * 2 * C * kb);
+  w.swl = (int32_t *)(b + off);
+  off = align256(off + sizeof(int32_t) * (1 + 4 * kb));
+  if (total) *total = off;
+  return w;
+}
+
+size_t panel_ws_bytes(int C, int kb) {
+  size_t t = 0;
+  carve(nullptr, C, kb, &t);
+  return t;
+}
+
+static inline size_t panel_lds(int C, int kb, int R) {
+  const int Q = 2 * C;
+  size_t b = sizeof(double) * ((size_t)kb * Q * R + 2 * (size_t)Q * kb + 4 * C + Q);
+  b += sizeof(int) * (4 + kb + 4 * kb);
+  return align256(b);
+}
+
+PanelGeom panel_geometry(int C, int64_t mp, int kb) {
+  PanelGeom g{0, 0, 0};
+  if (mp <= 0 || kb <= 0 || kb > PKBMAX) return g;
+  // largest row count per workgroup that fits in LDS (and one row per thread)
+  int rmax = PNT;
+  while (rmax > 1 && panel_lds(C, kb, rmax) > PLDS_BUDGET) --rmax;
+  // aim for about 64 workgroups: fewer makes the per-column barrier cheaper, more
+  // spreads the rank-1 work; never below 8 rows each
+  static int target = 0;
+  if (target == 0) {
+    const char *e = getenv("MPLU_PANEL_WGS");
+    target = e ? atoi(e) : 64;
+    if (target < 1) target = 64;
+  }
+  int64_t R = (mp + target - 1) / target;
+  if (R < 8) R = 8;
+  if (R > rmax) R = rmax;
+  int64_t G = (mp + R - 1) / R;
+  if (G > PGMAX) return g;
+  g.G = (int)G;
+  g.R = (int)R;
+  g.lds = panel_lds(C, kb, (int)R);
+  return g;
+}
+
+struct PanelArgs {
+  ZM A;
+  int64_t j, m;
+  int kb, R, G;
+  int32_t *ipiv, *info;
+  PanelWS w;
+};
+
+// lexicographic comparison of renormalised components: a strict total order that
+// agrees with the value order of non-overlapping expansions (ties between equal
+// representations are broken by the row index)
+template <int C>
+__device__ __forceinline__ bool better(const double (&a)[C], int ia, const double (&b)[C],
+                                       int ib) {
+  if (ia == INT_MAX) return false;
+  if (ib == INT_MAX) return true;
+  int c = 0;
+#pragma unroll
+  for (int k = C - 1; k >= 0; --k) c = (a[k] > b[k]) ? 1 : ((a[k] < b[k]) ? -1 : c);
+  return c > 0 || (c == 0 && ia < ib);
+}
+
+// argmax over the workgroup; every thread returns with the winner
+template <int C>
+__device__ __forceinline__ void block_argmax(double (&v)[C], int &idx, double *sv, int *si) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    double ov[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ov[c] = __shfl_xor(v[c], off);
+    const int oi = __shfl_xor(idx, off);
+    if (better<C>(ov, oi, v, idx)) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = ov[c];
+      idx = oi;
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) sv[w * C + c] = v[c];
+    si[w] = idx;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ww = 0; ww < PNT / 64; ++ww) {
+    double ov[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) ov[c] = sv[ww * C + c];
+    const int oi = si[ww];
+    if (better<C>(ov, oi, v, idx)) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = ov[c];
+      idx = oi;
+    }
+  }
+  __syncthreads();
+}
+
+// grid-wide barrier over G co-resident workgroups: monotonic arrival counter, a
+// generation word released by the last arrival, and a bounded wait whose expiry is
+// sticky (every later wait returns at once) so that no wave can wait forever
+__device__ __forceinline__ void grid_sync(unsigned *bar, unsigned G, unsigned &gen) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned target = gen + 1;
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (arrived == G * target) {
+      __hip_atomic_store(&bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > SPIN_LIMIT) {
+          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+  gen += 1;
+}
+
+template <int C>
+__global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
+  extern __shared__ double smem[];
+  constexpr int Q = 2 * C;
+  const int kb = a.kb, R = a.R, G = a.G;
+  const int g = blockIdx.x, t = threadIdx.x;
+  const int64_t mp = a.m - a.j;
+  const int64_t r0 = (int64_t)g * R;
+  const int nr = (int)(mp - r0 < R ? (mp - r0 > 0 ? mp - r0 : 0) : R);
+  const ZM A = a.A;
+  const int64_t j = a.j;
+
+  double *sA = smem;                             // [kb][Q][R]
+  double *sPiv = sA + (size_t)kb * Q * R;        // [Q][kb]
+  double *sRowK = sPiv + Q * kb;                 // [Q][kb]
+  double *sRedV = sRowK + Q * kb;                // [4][C]
+  double *sRcp = sRedV + 4 * C;                  // [Q]
+  int *sRedI = (int *)(sRcp + Q);                // [4]
+  int *sPivRow = sRedI + 4;                      // [kb]
+  int *sList = sPivRow + kb;                     // [4 kb]
+
+  // load this workgroup's rows of the panel
+  for (int e = t; e < nr * kb * Q; e += PNT) {
+    const int r = e % nr, rest = e / nr, c = rest % kb, q = rest / kb;
+    sA[((size_t)c * Q + q) * R + r] = A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)];
+  }
+  __syncthreads();
+
+  unsigned gen = 0;
+  for (int k = 0; k < kb; ++k) {
+    const int par = k & 1;
+    double *part = a.w.part + (size_t)par * PGMAX * (C + 1);
+    double *cand = a.w.cand + (size_t)par * PGMAX * Q * kb;
+    double *rowk = a.w.rowk + (size_t)par * Q * kb;
+
+    // (1) local pivot candidate among rows >= k
+    double v[C];
+    int idx = INT_MAX;
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = 0.0;
+    if (t < nr && r0 + t >= k) {
+      double re[C], im[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        re[c] = sA[((size_t)k * Q + c) * R + t];
+        im[c] = sA[((size_t)k * Q + C + c) * R + t];
+      }
+      mp::cabs1<C>(re, im, v);
+      idx = (int)(r0 + t);
+    }
+    block_argmax<C>(v, idx, sRedV, sRedI);
+
+    // (2) publish candidate and, if owned, row k
+    if (t == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) part[g * (C + 1) + c] = v[c];
+      part[g * (C + 1) + C] = (idx == INT_MAX) ? -1.0 : (double)idx;
+    }
+    if (idx != INT_MAX) {
+      const int lr = (int)(idx - r0);
+      for (int e = t; e < Q * kb; e += PNT) {
+        const int q = e / kb, c = e % kb;
+        cand[((size_t)g * Q + q) * kb + c] = sA[((size_t)c * Q + q) * R + lr];
+      }
+    }
+    if (k >= r0 && k < r0 + nr) {
+      const int lr = (int)(k - r0);
+      for (int e = t; e < Q * kb; e += PNT) {
+        const int q = e / kb, c = e % kb;
+        rowk[q * kb + c] = sA[((size_t)c * Q + q) * R + lr];
+      }
+    }
+    grid_sync(a.w.bar, (unsigned)G, gen);
+
+    // (3) global winner
+    double bv[C];
+    int bi = INT_MAX;
+#pragma unroll
+    for (int c = 0; c < C; ++c) bv[c] = 0.0;
+    if (t < G) {
+      const double ix = part[t * (C + 1) + C];
+      if (ix >= 0.0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) bv[c] = part[t * (C + 1) + c];
+        bi = (int)ix;
+      }
+    }
+    block_argmax<C>(bv, bi, sRedV, sRedI);
+    const int p = bi;
+    const int gp = p / R;
+    for (int e = t; e < Q * kb; e += PNT) {
+      sPiv[e] = cand[(size_t)gp * Q * kb + e];
+      sRowK[e] = rowk[e];
+    }
+    bool zero = true;
+#pragma unroll
+    for (int c = 0; c < C; ++c) zero = zero && (bv[c] == 0.0);
+    if (t == 0) {
+      sPivRow[k] = p;
+      if (g == 0) {
+        a.ipiv[j + k] = (int32_t)(j + p + 1);
+        if (zero && *a.info == 0) *a.info = (int32_t)(j + k + 1);
+      }
+    }
+    __syncthreads();
+
+    if (!zero) {
+      // (4) interchange rows k and p inside this workgroup's rows
+      if (p != k) {
+        if (p >= r0 && p < r0 + nr) {
+          const int lr = (int)(p - r0);
+          for (int e = t; e < Q * kb; e += PNT) {
+            const int q = e / kb, c = e % kb;
+            sA[((size_t)c * Q + q) * R + lr] = sRowK[e];
+          }
+        }
+        if (k >= r0 && k < r0 + nr) {
+          const int lr = (int)(k - r0);
+          for (int e = t; e < Q * kb; e += PNT) {
+            const int q = e / kb, c = e % kb;
+            sA[((size_t)c * Q + q) * R + lr] = sPiv[e];
+          }
+        }
+      }
+      // (5) reciprocal of the pivot
+      if (t == 0) {
+        double pr[C], pi[C], rr[C], ri[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          pr[c] = sPiv[c * kb + k];
+          pi[c] = sPiv[(C + c) * kb + k];
+        }
+        mp::zrecip<C>(pr, pi, rr, ri);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          sRcp[c] = rr[c];
+          sRcp[C + c] = ri[c];
+        }
+      }
+      __syncthreads();
+      // (6) multipliers l_i = a_ik / a_kk for rows below k
+      if (t < nr && r0 + t > k) {
+        double xr[C], xi[C], rr[C], ri[C], lr_[C], li[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          xr[c] = sA[((size_t)k * Q + c) * R + t];
+          xi[c] = sA[((size_t)k * Q + C + c) * R + t];
+          rr[c] = sRcp[c];
+          ri[c] = sRcp[C + c];
+        }
+        mp::zmul<C>(xr, xi, rr, ri, lr_, li);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          sA[((size_t)k * Q + c) * R + t] = lr_[c];
+          sA[((size_t)k * Q + C + c) * R + t] = li[c];
+        }
+      }
+      __syncthreads();
+      // (7) rank-1 update of this workgroup's rows below k, columns right of k
+      const int lo = (int)(k + 1 - r0 > 0 ? k + 1 - r0 : 0);
+      const int cnt = nr - lo;
+      const int ncol = kb - k - 1;
+      if (cnt > 0 && ncol > 0) {
+        for (int e = t; e < cnt * ncol; e += PNT) {
+          const int r = lo + e % cnt;
+          const int c = k + 1 + e / cnt;
+          double xr[C], xi[C], lr_[C], li[C], ur[C], ui[C];
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc) {
+            xr[cc] = sA[((size_t)c * Q + cc) * R + r];
+            xi[cc] = sA[((size_t)c * Q + C + cc) * R + r];
+            lr_[cc] = sA[((size_t)k * Q + cc) * R + r];
+            li[cc] = sA[((size_t)k * Q + C + cc) * R + r];
+            ur[cc] = sPiv[cc * kb + c];
+            ui[cc] = sPiv[(C + cc) * kb + c];
+          }
+          mp::zfms<C>(xr, xi, lr_, li, ur, ui, xr, xi);
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc) {
+            sA[((size_t)c * Q + cc) * R + r] = xr[cc];
+            sA[((size_t)c * Q + C + cc) * R + r] = xi[cc];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // write this workgroup's rows back
+  for (int e = t; e < nr * kb * Q; e += PNT) {
+    const int r = e % nr, rest = e / nr, c = rest % kb, q = rest / kb;
+    A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)] = sA[((size_t)c * Q + q) * R + r];
+  }
+
+  // workgroup 0: the interchange list for the columns outside the panel.  Replaying the
+  // kb swaps on the touched rows gives, for every touched row, the row whose content
+  // finally lands there (one wave; the search over touched rows uses a ballot).
+  if (g == 0 && t < 64) {
+    int *rows = sList, *cont = sList + 2 * kb;
+    int nt = 0;
+    for (int k = 0; k < kb; ++k) {
+      const int pr[2] = {k, sPivRow[k]};
+      int slot[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        unsigned long long hit = 0;
+        for (int base = 0; base < nt; base += 64) {
+          const int e = base + t;
+          const bool f = (e < nt) && (rows[e] == pr[h]);
+          const unsigned long long b = __ballot(f);
+          if (b && !hit) hit = ((unsigned long long)(base + __ffsll((long long)b) - 1)) + 1ull;
+        }
+        if (hit) {
+          slot[h] = (int)(hit - 1);
+        } else {
+          if (t == 0) {
+            rows[nt] = pr[h];
+            cont[nt] = pr[h];
+          }
+          slot[h] = nt;
+          nt += 1;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (t == 0 && slot[0] != slot[1]) {
+        const int tmp = cont[slot[0]];
+        cont[slot[0]] = cont[slot[1]];
+        cont[slot[1]] = tmp;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (t == 0) {
+      int cntl = 0;
+      int32_t *dst = a.w.swl + 1, *src = a.w.swl + 1 + 2 * kb;
+      for (int e = 0; e < nt; ++e)
+        if (cont[e] != rows[e]) {
+          dst[cntl] = (int32_t)(j + rows[e]);
+          src[cntl] = (int32_t)(j + cont[e]);
+          ++cntl;
+        }
+      a.w.swl[0] = cntl;
+      if (__hip_atomic_load(&a.w.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+        *a.info = -9999;
+    }
+  }
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_laswp(ZM A, int64_t c0, int64_t c1, int64_t n,
+                                               const int32_t *swl, int kb) {
+  const int cnt = swl[0];
+  const int32_t *dst = swl + 1, *src = swl + 1 + 2 * kb;
+  const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t ncols = c0 + (n - c1);
+  if (w >= ncols || cnt == 0) return;
+  const int64_t col = w < c0 ? w : c1 + (w - c0);
+  constexpr int Q = 2 * C;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double *base = A.p + (int64_t)q * A.ps + col * A.ld;
+    double v[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = lane + 64 * h;
+      v[h] = (e < cnt) ? base[src[e]] : 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = lane + 64 * h;
+      if (e < cnt) base[dst[e]] = v[h];
+    }
+  }
+}
+
+template <int C>
+static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
+                                 int32_t *info, void *ws, hipStream_t s) {
+  const PanelGeom geo = panel_geometry(C, m - j, kb);
+  if (geo.G == 0) return hipErrorInvalidValue;
+  PanelArgs a;
+  a.A = A;
+  a.j = j;
+  a.m = m;
+  a.kb = kb;
+  a.R = geo.R;
+  a.G = geo.G;
+  a.ipiv = ipiv;
+  a.info = info;
+  a.w = carve(ws, C, kb, nullptr);
+  static bool attr_done[5] = {false, false, false, false, false};
+  if (!attr_done[C]) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_panel<C>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)PLDS_BUDGET);
+    if (e != hipSuccess) return e;
+    attr_done[C] = true;
+  }
+  hipError_t e = launch_fill_i32((int32_t *)a.w.bar, 0, 4, s);
+  if (e != hipSuccess) return e;
+  void *args[] = {&a};
+  return hipLaunchCooperativeKernel((const void *)k_panel<C>, dim3(geo.G), dim3(PNT), args,
+                                    (unsigned)geo.lds, s);
+}
+
+hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
+                        int32_t *info, void *ws, hipStream_t s) {
+  switch (C) {
+    case 2: return launch_panel_t<2>(A, j, m, kb, ipiv, info, ws, s);
+    case 3: return launch_panel_t<3>(A, j, m, kb, ipiv, info, ws, s);
+    case 4: return launch_panel_t<4>(A, j, m, kb, ipiv, info, ws, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
+                        int kb, hipStream_t s) {
+  const int64_t ncols = c0 + (n - c1);
+  if (ncols <= 0) return hipSuccess;
+  PanelWS w = carve(const_cast<void *>(ws), C, kb, nullptr);
+  const int64_t blocks = (ncols + 3) / 4;
+  switch (C) {
+    case 2: hipLaunchKernelGGL(k_laswp<2>, dim3((unsigned)blocks), dim3(256), 0, s, A, c0, c1, n, w.swl, kb); break;
+    case 3: hipLaunchKernelGGL(k_laswp<3>, dim3((unsigned)blocks), dim3(256), 0, s, A, c0, c1, n, w.swl, kb); break;
+    case 4: hipLaunchKernelGGL(k_laswp<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, c0, c1, n, w.swl, kb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mplu

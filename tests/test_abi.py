@@ -1,0 +1,84 @@
+"""The C ABI: the library loads, exports every entry point declared in include/mplu.h,
+and rejects bad arguments before touching the GPU (LAPACK-style -i codes)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "mplu.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(mplu_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2403_16013_amd as m
+
+    return m.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_version_and_strerror(L):
+    assert L.mplu_version() >= 10000
+    assert L.mplu_strerror(0) == b"success"
+    assert L.mplu_strerror(-100) == b"workspace too small"
+    assert L.mplu_strerror(-3) == b"invalid argument"
+
+
+def test_argument_checks(L):
+    import paper_2403_16013_amd as m
+
+    z = m.ZMat(0x1000, 8, 64)
+    null = m.ZMat(0, 8, 64)
+    ip = ct.c_void_p(0x2000)
+    inf = ct.c_void_p(0x3000)
+    wk = ct.c_void_p(0x10000)
+    # precision
+    assert L.mplu_zgetrf(5, 8, 8, z, ip, inf, None, wk, 1 << 30, None) == -1
+    assert L.mplu_zgetrf(2, -1, 8, z, ip, inf, None, wk, 1 << 30, None) == -2
+    assert L.mplu_zgetrf(2, 8, -1, z, ip, inf, None, wk, 1 << 30, None) == -3
+    assert L.mplu_zgetrf(2, 8, 8, null, ip, inf, None, wk, 1 << 30, None) == -4
+    assert L.mplu_zgetrf(2, 9, 8, z, ip, inf, None, wk, 1 << 30, None) == -4   # ld < m
+    assert L.mplu_zgetrf(2, 8, 9, z, ip, inf, None, wk, 1 << 30, None) == -4   # stride
+    assert L.mplu_zgetrf(2, 8, 8, z, None, inf, None, wk, 1 << 30, None) == -5
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, None, None, wk, 1 << 30, None) == -6
+    bad = m.Opts(-1, 1, 0, 0, 0)
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
+    bad = m.Opts(64, 9, 0, 0, 0)
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, None, ct.c_void_p(0x10001), 1 << 30, None) == -8
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, None, wk, 16, None) == -100
+    assert L.mplu_zgetrs(2, b"X", 8, 1, z, ip, z, wk, 1 << 30, None) == -2
+    assert L.mplu_zgetrs(2, b"N", 8, 1, z, None, z, wk, 1 << 30, None) == -6
+    assert L.mplu_zgetrs(2, b"N", 8, 2, z, ip, m.ZMat(0x1000, 8, 8), wk, 1 << 30, None) == -7
+    assert L.mplu_zgesv(2, 8, 1, z, ip, z, None, None, wk, 1 << 30, None) == -7
+    assert L.mplu_zgemm(2, b"Q", b"N", 4, 4, 4, 1, z, z, 0, z, 0, None, wk, 0, None) == -2
+    assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 2, z, z, 0, z, 0, None, wk, 0, None) == -7
+    assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 2, z, 0, None, wk, 0, None) == -10
+    assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 0, z, 7, None, wk, 0, None) == -12
+    assert L.mplu_zrenorm(2, 8, 8, null, None) == -4
+    assert L.mplu_zconvert(2, 7, 8, 8, z, z, None) == -2
+
+
+def test_workspace_queries(L):
+    import paper_2403_16013_amd as m
+
+    sz = ct.c_size_t()
+    assert L.mplu_zgetrf_wsbytes(2, 4096, 4096, None, ct.byref(sz)) == 0
+    a = sz.value
+    o = m.Opts(128, 1, 0, 0, 0)
+    assert L.mplu_zgetrf_wsbytes(4, 4096, 4096, ct.byref(o), ct.byref(sz)) == 0
+    assert sz.value > a > 0
+    assert L.mplu_zgetrs_wsbytes(2, 100, 3, ct.byref(sz)) == 0
+    assert sz.value >= 100 * 3 * 4 * 8
+    assert L.mplu_zgesv_wsbytes(3, 100, 3, None, ct.byref(sz)) == 0

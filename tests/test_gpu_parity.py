@@ -1,0 +1,236 @@
+"""GPU parity against the CPU oracle, through the C ABI (libmplu.so via the binding).
+
+Sizes here span several tiles / panels and a ragged tail while the oracle still finishes
+in seconds.  Bounds:
+  * products: |gpu - oracle| <= 4 (k+4) u (sum |a||b| + |c|) elementwise (cabs1 measure)
+  * LU: identical pivots where the pivot gap is clear, factors within 100 n u
+    (normwise), solutions within 10 n kappa u of the oracle's, backward error
+    eta <= 10 n u from an exact residual
+  * exactly representable factorisations: bit for bit on every path.
+"""
+import numpy as np
+import pytest
+
+import synthgen
+from helpers import U_FMT, exact_lu_case, gemm_tol, pivot_gaps_clear, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CS = [2, 3, 4]
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2403_16013_amd as m
+
+    m.lib()
+    return m
+
+
+def sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("C", CS)
+def test_renorm_matches_oracle_values(mp, orc, C):
+    P = synthgen.uniform(77, 33, C, 1)
+    T = to_dev(P)
+    mp.renorm_(T)
+    got = to_host(T)
+    ref = orc.canon(P)
+    d = orc.diff(got, ref)
+    assert np.all(d == 0), "renormalised value changed"
+    if C == 2:
+        assert np.array_equal(got, ref)
+    # non-overlap of consecutive components
+    for c in range(C - 1):
+        hi, lo = got[:, c], got[:, c + 1]
+        assert np.all(np.abs(lo) <= np.spacing(np.abs(hi)) / 2)
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["3m", "4m"])
+@pytest.mark.parametrize("ops", [("N", "N"), ("C", "N"), ("N", "C"), ("T", "T")])
+def test_gemm_vs_oracle(mp, orc, C, method, ops):
+    opA, opB = ops
+    m, n, k = 70, 45, 37
+    A = orc.canon(synthgen.uniform(m if opA == "N" else k, k if opA == "N" else m, C, 10))
+    B = orc.canon(synthgen.uniform(k if opB == "N" else n, n if opB == "N" else k, C, 11))
+    Cm = orc.canon(synthgen.uniform(m, n, C, 12))
+    for alpha in (1, -1):
+        ref = orc.gemm(A, B, Cm, method=3 if method == "3m" else 4, opA=opA, opB=opB,
+                       alpha_sign=alpha)
+        Td = to_dev(Cm)
+        mp.gemm(to_dev(A), to_dev(B), Td, opA=opA, opB=opB, alpha=alpha, method=method)
+        got = to_host(Td)
+        d = orc.diff(got, ref)
+        tol = gemm_tol(A, B, Cm, opA, opB, C, k)
+        assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)
+    # beta = 0
+    ref = orc.gemm(A, B, None, method=3 if method == "3m" else 4, opA=opA, opB=opB)
+    got = to_host(mp.gemm(to_dev(A), to_dev(B), None, opA=opA, opB=opB, method=method))
+    d = orc.diff(got, ref)
+    tol = gemm_tol(A, B, None, opA, opB, C, k)
+    assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["3m", "4m"])
+def test_gemm_exact_on_dyadic_data(mp, C, method):
+    rng = np.random.default_rng(5)
+    m, n, k = 67, 41, 29
+    Ac = (rng.integers(-99, 100, (m, k)) + 1j * rng.integers(-99, 100, (m, k))) / 8
+    Bc = (rng.integers(-99, 100, (k, n)) + 1j * rng.integers(-99, 100, (k, n))) / 8
+    Cc = (rng.integers(-99, 100, (m, n)) + 1j * rng.integers(-99, 100, (m, n))) / 8
+    Td = to_dev(synthgen.planes_from_complex(Cc, C))
+    mp.gemm(to_dev(synthgen.planes_from_complex(Ac, C)), to_dev(synthgen.planes_from_complex(Bc, C)),
+            Td, alpha=-1, method=method)
+    got = to_host(Td)
+    assert np.array_equal((got[0, 0] + 1j * got[1, 0]).T, Cc - Ac @ Bc)
+    assert not np.any(got[:, 1:])
+
+
+@pytest.mark.parametrize("C", CS)
+def test_gemm_real_data_3m_equals_4m_and_zero_imag(mp, orc, C):
+    m, n, k = 40, 36, 50
+    A = orc.canon(synthgen.uniform(m, k, C, 20))
+    B = orc.canon(synthgen.uniform(k, n, C, 21))
+    A[1] = 0
+    B[1] = 0
+    g3 = to_host(mp.gemm(to_dev(A), to_dev(B), None, method="3m"))
+    g4 = to_host(mp.gemm(to_dev(A), to_dev(B), None, method="4m"))
+    assert not np.any(g3[1])
+    d = orc.diff(g3, g4)
+    tol = gemm_tol(A, B, None, "N", "N", C, k)
+    assert np.all(np.abs(d.real) <= tol)
+
+
+def _lu_parity(mp, orc, C, n, panel, method, seed, m=None):
+    m = n if m is None else m
+    A = orc.canon(synthgen.uniform(m, n, C, seed))
+    LUo, ipo, info_o = orc.getf2(A)
+    T = to_dev(A)
+    ipiv, info = mp.getrf(T, panel=panel, method=method)
+    sync()
+    LUg = to_host(T)
+    ipg = ipiv.cpu().numpy()
+    assert int(info.item()) == info_o == 0
+    k_clear = pivot_gaps_clear(orc.hi_complex(LUo))
+    assert np.array_equal(ipg[:k_clear], ipo[:k_clear])
+    if k_clear == min(m, n):
+        d = orc.diff(LUg, LUo)
+        scale = np.abs(orc.hi_complex(LUo)).max()
+        assert np.abs(d).max() <= 100 * max(m, n) * U_FMT[C] * scale
+    return A, LUg, ipg, LUo, ipo
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["3m", "4m"])
+def test_getrf_blocked_vs_oracle(mp, orc, C, method):
+    _lu_parity(mp, orc, C, 200, 64, method, 30 + C)
+
+
+@pytest.mark.parametrize("C", [2])
+def test_getrf_unblocked_c1(mp, orc, C):
+    """n = 64, panel = n (the unblocked "Normal LU"), 4M."""
+    _lu_parity(mp, orc, C, 64, 64, "4m", 0)
+
+
+@pytest.mark.parametrize("shape", [(150, 100), (100, 150), (257, 129)])
+def test_getrf_rectangular(mp, orc, shape):
+    m, n = shape
+    _lu_parity(mp, orc, 2, n, 32, "3m", 40, m=m)
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("trans", ["N", "C"])
+def test_getrs_vs_oracle(mp, orc, C, trans):
+    n, nrhs = 150, 3
+    A = orc.canon(synthgen.uniform(n, n, C, 50 + C))
+    B = orc.canon(synthgen.uniform(n, nrhs, C, 60 + C))
+    LUo, ipo, _ = orc.getf2(A)
+    Xo = orc.getrs(LUo, ipo, B, trans)
+    T = to_dev(A)
+    ipiv, info = mp.getrf(T, panel=64, method="3m")
+    Bd = to_dev(B)
+    mp.getrs(T, ipiv, Bd, trans=trans)
+    Xg = to_host(Bd)
+    kappa = np.linalg.cond(orc.hi_complex(A), np.inf)
+    d = orc.diff(Xg, Xo)
+    assert np.abs(d).max() / np.abs(orc.hi_complex(Xo)).max() <= 10 * n * kappa * U_FMT[C]
+    if trans == "C":
+        AH = np.ascontiguousarray(np.transpose(A, (0, 1, 3, 2)))
+        AH[1] *= -1
+        eta = orc.backward_error(AH, Xg, B)
+    else:
+        eta = orc.backward_error(A, Xg, B)
+    assert eta <= 10 * n * U_FMT[C]
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["3m", "4m"])
+def test_exactly_representable_lu_bitwise(mp, C, method):
+    for n, panel in ((64, 64), (150, 32)):
+        A, L, U, ipiv_want = exact_lu_case(n, C, 7 + n)
+        T = to_dev(A)
+        ipiv, info = mp.getrf(T, panel=panel, method=method)
+        sync()
+        assert int(info.item()) == 0
+        assert np.array_equal(ipiv.cpu().numpy(), ipiv_want)
+        got = to_host(T)
+        assert np.array_equal((got[0, 0] + 1j * got[1, 0]).T, np.tril(L, -1) + U)
+        assert not np.any(got[:, 1:])
+        xt = synthgen.planes_from_complex(np.arange(1, n + 1) * (1 + 1j), C)
+        xc = (xt[0, 0] + 1j * xt[1, 0]).T
+        Bd = to_dev(synthgen.planes_from_complex((A[0, 0] + 1j * A[1, 0]).T @ xc, C))
+        mp.getrs(T, ipiv, Bd)
+        assert np.array_equal(to_host(Bd), xt)
+
+
+@pytest.mark.parametrize("C", [2, 4])
+def test_zero_column_sets_info(mp, orc, C):
+    n = 96
+    A = orc.canon(synthgen.uniform(n, n, C, 70))
+    A[:, :, 70, :] = 0.0
+    _, _, info_o = orc.getf2(A)
+    T = to_dev(A)
+    _, info = mp.getrf(T, panel=32)
+    sync()
+    assert int(info.item()) == info_o == 71
+    T = to_dev(np.zeros((2, C, 40, 40)))
+    ipiv, info = mp.getrf(T, panel=16)
+    sync()
+    assert int(info.item()) == 1
+    assert list(ipiv.cpu().numpy()) == list(range(1, 41))
+
+
+def test_empty_and_tiny(mp, orc):
+    import torch
+
+    T = torch.zeros((2, 2, 0, 1), dtype=torch.float64, device="cuda")
+    ipiv, info = mp.getrf(T, panel=64)
+    sync()
+    assert int(info.item()) == 0
+    A = orc.canon(synthgen.uniform(1, 1, 2, 3))
+    T = to_dev(A)
+    ipiv, info = mp.getrf(T)
+    sync()
+    assert int(ipiv.item()) == 1 and np.array_equal(to_host(T), A)
+
+
+@pytest.mark.parametrize("method", ["3m", "4m"])
+def test_deterministic(mp, orc, method):
+    A = orc.canon(synthgen.uniform(300, 300, 2, 80))
+    outs = []
+    for _ in range(2):
+        T = to_dev(A)
+        ipiv, info = mp.getrf(T, panel=64, method=method)
+        sync()
+        outs.append((to_host(T), ipiv.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
