@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark: effective complex GFLOPS of multi-component LU on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic input: canonicalised
+complex double-double A (n = 4096, entries uniform[-1,1], lower components
+c_k = c_{k-1} 2^-53 U(-1,1)), blocked right-looking LU with partial pivoting (panel 64,
+3M trailing update), then the forward / backward solve for b = A 1.  All inputs are
+resident in HBM before the timed region; each step factors its own copy of A.
+
+value = 8 n^3 / 3 / t_step (the LAPACK zgetrf operation count; the solve is inside the
+step but not counted).  Besides the headline line, the JSON carries: the backward error
+of the last solve (exact-enough residual computed on the GPU in quadruple-double), the
+4M / triple-double / quadruple-double variants, the roofline of the dominant kernel (the
+3M trailing-update GEMM, timed live with HIP events) and the CPU oracle baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096] [--panel 64]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as ct
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("effective complex GFLOPS of DD/TD/QD getrf at n=4096 (3M vs 4M vs split-MFMA) "
+          "+ backward err")
+PEAK_FP64_TFLOPS = 78.6   # 256 CU x 64 FP64 lanes/clk x 2 (FMA) x 2.4 GHz
+# algorithmic FP64 flops of one real multiply-accumulate in the level accumulator of the
+# trailing update (FMA counted as 2; 12 / 45 / 112 FP64 instructions for DD / TD / QD);
+# 3M uses three real MACs per complex MAC, 4M four
+FLOPS_PER_REAL_MAC = {2: 15, 3: 51, 4: 122}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=4096)
+    p.add_argument("--panel", type=int, default=64)
+    p.add_argument("--method", default="3m")
+    p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-roofline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target length of the CPU oracle sample")
+    return p.parse_args()
+
+
+def eff_gflops(n, seconds):
+    return 8.0 * n ** 3 / 3.0 / seconds / 1e9
+
+
+def backward_error(mp, torch, A0, X, B0):
+    """eta = ||b - A x||_inf / (||A||_inf ||x||_inf); residual formed by the library in
+    quadruple-double (widening is exact), norms from the leading components."""
+    A4 = mp.convert(A0, 4)
+    X4 = mp.convert(X, 4)
+    R4 = mp.convert(B0, 4)
+    mp.gemm(A4, X4, R4, alpha=-1, method="4m")
+    hi = lambda T: torch.complex(T[0, 0], T[1, 0]).transpose(0, 1)
+    nr = hi(R4).abs().max().item()
+    nA = hi(A0).abs().sum(dim=1).max().item()
+    nx = hi(X).abs().max().item()
+    return nr / (nA * nx)
+
+
+def make_problem(mp, torch, synthgen, n, C, seed=0):
+    A0 = torch.from_numpy(synthgen.uniform(n, n, C, seed)).cuda()
+    mp.renorm_(A0)
+    X1 = torch.from_numpy(synthgen.ones(n, 1, C)).cuda()
+    B0 = mp.gemm(A0, X1, None, method="4m")   # b = A 1 in the working precision
+    return A0, B0
+
+
+def time_gesv(mp, torch, A0, B0, steps, warmup, panel, method):
+    """Factor + solve `steps` resident copies back to back; returns (ms/step, X, info)."""
+    C, n = A0.shape[1], A0.shape[2]
+    nb = ct.c_size_t()
+    o = mp._opts(panel, method)
+    mp.lib().mplu_zgesv_wsbytes(C, n, 1, ct.byref(o), ct.byref(nb))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    As = [A0.clone() for _ in range(warmup + steps)]
+    Bs = [B0.clone() for _ in range(warmup + steps)]
+    for w in range(warmup):
+        mp.gesv(As[w], Bs[w], panel=panel, method=method, work=work)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    infos = []
+    t0 = time.perf_counter()
+    ev0.record()
+    for s in range(steps):
+        _, info = mp.gesv(As[warmup + s], Bs[warmup + s], panel=panel, method=method, work=work)
+        infos.append(info)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / steps
+    info = max(int(i.item()) for i in infos)
+    X = Bs[-1]
+    del As
+    return ms, wall, X, info
+
+
+def gemm_roofline(mp, torch, A0, panel, method):
+    """Replay the trailing updates of one factorisation (m = n - j - K, k = K for every
+    panel step j) through mplu_zgemm on the stream, each launch bracketed by HIP events."""
+    C, n = A0.shape[1], A0.shape[2]
+    M = A0.clone()
+    L = mp.lib()
+    ld, ps = n, n * n
+    base = M.data_ptr()
+    meth = mp._METHODS[method]
+    stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def sub(i, j):
+        return mp.ZMat(base + 8 * (j * ld + i), ld, ps)
+
+    launches = []
+    for j in range(0, n - panel, panel):
+        r = n - j - panel
+        if r <= 0:
+            break
+        launches.append((j, r))
+    # warm up the kernel once
+    rc = L.mplu_zgemm(C, b"N", b"N", launches[0][1], launches[0][1], panel, -1,
+                      sub(panel, 0), sub(0, panel), 1, sub(panel, panel), meth, None, None, 0,
+                      stream)
+    assert rc == 0, rc
+    torch.cuda.synchronize()
+    evs = []
+    for (j, r) in launches:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rc = L.mplu_zgemm(C, b"N", b"N", r, r, panel, -1, sub(j + panel, j), sub(j, j + panel),
+                          1, sub(j + panel, j + panel), meth, None, None, 0, stream)
+        e1.record()
+        assert rc == 0, rc
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    total_ms = sum(a.elapsed_time(b) for a, b in evs)
+    macs = sum(r * r * panel for (_, r) in launches)
+    real_per_complex = 3 if method == "3m" else 4
+    flops = macs * real_per_complex * FLOPS_PER_REAL_MAC[C]
+    achieved = flops / (total_ms / 1e3) / 1e12
+    return {
+        "kernel": f"k_gemm<{C},{'3M' if method == '3m' else '4M'}> trailing update",
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+        "traffic": None,
+        "launches": len(launches),
+        "avg_launch_ms": round(total_ms / len(launches), 4),
+        "flops_per_launch": flops / len(launches),
+    }
+
+
+def cpu_baseline(synthgen, n, target_s):
+    """The oracle's unblocked 4M LU (the paper's Normal LU) on the same n x n DD matrix,
+    stopped after k columns so that the sample takes about target_s seconds."""
+    import oracle
+
+    threads = oracle.set_threads(0)
+    A = oracle.canon(synthgen.uniform(n, n, 2, 0))
+    # calibrate on one column
+    t0 = time.perf_counter()
+    oracle.getf2(A, kmax=1)
+    t1 = time.perf_counter() - t0
+    kmax = max(1, min(n, int(target_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.getf2(A, kmax=kmax)
+    dt = time.perf_counter() - t0
+    macs = sum((n - k - 1) ** 2 for k in range(kmax))
+    return {"value": round(8.0 * macs / dt / 1e9, 4), "unit": "GFLOPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"unblocked 4M LU of the n={n} DD matrix, first {kmax} columns "
+                      f"({macs:.3e} complex MACs, {dt:.1f} s, {threads} OpenMP threads)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2403_16013_amd as mp
+    import synthgen
+
+    n, panel, method = args.n, args.panel, args.method
+    print(f"[bench] DD n={n} panel={panel} {method}: building inputs", file=sys.stderr,
+          flush=True)
+    A0, B0 = make_problem(mp, torch, synthgen, n, 2)
+    ms, wall, X, info = time_gesv(mp, torch, A0, B0, args.steps, args.warmup, panel, method)
+    eta = backward_error(mp, torch, A0, X, B0)
+    print(f"[bench] DD {method}: {ms:.2f} ms/step info={info} eta={eta:.3e}", file=sys.stderr,
+          flush=True)
+    line = {
+        "metric": METRIC,
+        "value": round(eff_gflops(n, ms / 1e3), 2),
+        "unit": "GFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"complex double-double gesv (getrf + getrs), n={n}, panel {panel}, "
+                               f"{method.upper()} trailing update, A uniform[-1,1] DD, b = A*1",
+                   "n": n, "prec": "DD", "panel": panel, "method": method, "nrhs": 1},
+        "eta": eta,
+        "info": info,
+        "wall_s_timed": round(wall, 3),
+    }
+    if not args.no_roofline:
+        line["roofline"] = gemm_roofline(mp, torch, A0, panel, method)
+        print(f"[bench] roofline {line['roofline']}", file=sys.stderr, flush=True)
+    if not args.no_variants:
+        var = {}
+        for (C, meth, pnl, steps) in ((2, "4m", panel, 2), (2, "3m", 128, 2), (3, "3m", panel, 1),
+                                      (4, "3m", panel, 1)):
+            A, B = (A0, B0) if C == 2 else make_problem(mp, torch, synthgen, n, C)
+            vms, _, VX, vinfo = time_gesv(mp, torch, A, B, steps, 1, pnl, meth)
+            veta = backward_error(mp, torch, A, VX, B)
+            key = f"{['', '', 'DD', 'TD', 'QD'][C]}_{meth}_K{pnl}"
+            var[key] = {"ms": round(vms, 3), "gflops": round(eff_gflops(n, vms / 1e3), 2),
+                        "eta": veta, "info": vinfo}
+            print(f"[bench] variant {key}: {var[key]}", file=sys.stderr, flush=True)
+            del A, B, VX
+            torch.cuda.empty_cache()
+        line["variants"] = var
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(synthgen, n, args.cpu_seconds)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

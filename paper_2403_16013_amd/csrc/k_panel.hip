@@ -22,7 +22,8 @@ static constexpr int PNT = 256;        // threads per panel workgroup
 static constexpr int PGMAX = 256;      // max workgroups (one partial per thread)
 static constexpr int PKBMAX = 128;     // max panel width
 static constexpr size_t PLDS_BUDGET = 160 * 1024;
-static constexpr unsigned SPIN_LIMIT = 1u << 25;  // ~2 s of s_sleep before giving up
+static constexpr unsigned SPIN_LIMIT = 1u << 26;  // ~2 s of s_sleep(1) before giving up
+static constexpr int32_t MPLU_SYNC_TIMEOUT = -9999;  // mirrors MPLU_INFO_SYNC_TIMEOUT
 
 // ------------------------------------------------------------------ workspace layout
 // [0, 256)              barrier words: count, generation, timeout flag
@@ -63,7 +64,7 @@ size_t panel_ws_bytes(int C, int kb) {
 
 static inline size_t panel_lds(int C, int kb, int R) {
   const int Q = 2 * C;
-  size_t b = sizeof(double) * ((size_t)kb * Q * R + 2 * (size_t)Q * kb + 4 * C + Q);
+  size_t b = sizeof(double) * ((size_t)kb * Q * R + 3 * (size_t)Q * kb + 4 * C + Q);
   b += sizeof(int) * (4 + kb + 4 * kb);
   return align256(b);
 }
@@ -152,35 +153,57 @@ __device__ __forceinline__ void block_argmax(double (&v)[C], int &idx, double *s
   __syncthreads();
 }
 
-// grid-wide barrier over G co-resident workgroups: monotonic arrival counter, a
-// generation word released by the last arrival, and a bounded wait whose expiry is
-// sticky (every later wait returns at once) so that no wave can wait forever
-__device__ __forceinline__ void grid_sync(unsigned *bar, unsigned G, unsigned &gen) {
-  __threadfence();
+// Cross-workgroup exchange.  Everything one workgroup publishes for the others goes
+// through agent-scope atomic stores and is read back with agent-scope atomic loads, which
+// are coherent across the XCDs' L2 caches without writing back or invalidating them.  A
+// store has reached the coherence point once the issuing wave's memory counter drains,
+// so a barrier arrival only needs that wait; no cache-wide fence is used.
+__device__ __forceinline__ void put(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double get(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Split grid barrier over G co-resident workgroups: a monotonic arrival counter and a
+// generation word written by the last arrival.  The wait is bounded and its expiry is
+// sticky (every later wait returns at once), so no wave can wait forever.
+__device__ __forceinline__ void grid_arrive(unsigned *bar, unsigned G, unsigned gen) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's published stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned target = gen + 1;
     const unsigned arrived =
-        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
-    if (arrived == G * target) {
-      __hip_atomic_store(&bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > SPIN_LIMIT) {
-          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
+        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (arrived == G * target)
+      __hip_atomic_store(&bar[1], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ void grid_wait(unsigned *bar, unsigned gen) {
+  if (threadIdx.x == 0) {
+    const unsigned target = gen + 1;
+    unsigned spins = 0;
+    while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > SPIN_LIMIT) {
+        __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
       }
     }
   }
   __syncthreads();
-  __threadfence();
-  gen += 1;
 }
 
+// element (row lr, column c, plane q) of this workgroup's rows in LDS
+#define SA(c, q, lr) sA[((size_t)(c) * Q + (q)) * R + (lr)]
+
+// Right-looking panel with look-ahead.  Loop invariant at the top of iteration k: in
+// this workgroup's rows, columns <= k are updated through step k-1, columns > k through
+// step k-2; the step k-1 update of columns > k ("pending") is applied while the barrier
+// of column k is in flight.  Rows published before that update are completed by their
+// readers, who hold the previous U row and find the row's multiplier in its column k-1.
 template <int C>
 __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   extern __shared__ double smem[];
@@ -194,29 +217,29 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   const int64_t j = a.j;
 
   double *sA = smem;                             // [kb][Q][R]
-  double *sPiv = sA + (size_t)kb * Q * R;        // [Q][kb]
-  double *sRowK = sPiv + Q * kb;                 // [Q][kb]
-  double *sRedV = sRowK + Q * kb;                // [4][C]
+  double *sPiv = sA + (size_t)kb * Q * R;        // [Q][kb]  U row k (current pivot row)
+  double *sRowK = sPiv + Q * kb;                 // [Q][kb]  row k before the interchange
+  double *sPrev = sRowK + Q * kb;                // [Q][kb]  U row k-1
+  double *sRedV = sPrev + Q * kb;                // [4][C]
   double *sRcp = sRedV + 4 * C;                  // [Q]
   int *sRedI = (int *)(sRcp + Q);                // [4]
   int *sPivRow = sRedI + 4;                      // [kb]
   int *sList = sPivRow + kb;                     // [4 kb]
 
-  // load this workgroup's rows of the panel
   for (int e = t; e < nr * kb * Q; e += PNT) {
     const int r = e % nr, rest = e / nr, c = rest % kb, q = rest / kb;
-    sA[((size_t)c * Q + q) * R + r] = A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)];
+    SA(c, q, r) = A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)];
   }
   __syncthreads();
 
-  unsigned gen = 0;
+  bool prev_zero = true;  // no pending update before column 0
   for (int k = 0; k < kb; ++k) {
     const int par = k & 1;
     double *part = a.w.part + (size_t)par * PGMAX * (C + 1);
     double *cand = a.w.cand + (size_t)par * PGMAX * Q * kb;
     double *rowk = a.w.rowk + (size_t)par * Q * kb;
 
-    // (1) local pivot candidate among rows >= k
+    // (1) local pivot candidate among rows >= k (column k is up to date)
     double v[C];
     int idx = INT_MAX;
 #pragma unroll
@@ -225,46 +248,74 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
       double re[C], im[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        re[c] = sA[((size_t)k * Q + c) * R + t];
-        im[c] = sA[((size_t)k * Q + C + c) * R + t];
+        re[c] = SA(k, c, t);
+        im[c] = SA(k, C + c, t);
       }
       mp::cabs1<C>(re, im, v);
       idx = (int)(r0 + t);
     }
     block_argmax<C>(v, idx, sRedV, sRedI);
 
-    // (2) publish candidate and, if owned, row k
+    // (2) publish the candidate (value, row, row contents) and, if owned, row k
     if (t == 0) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) part[g * (C + 1) + c] = v[c];
-      part[g * (C + 1) + C] = (idx == INT_MAX) ? -1.0 : (double)idx;
+      for (int c = 0; c < C; ++c) put(&part[g * (C + 1) + c], v[c]);
+      put(&part[g * (C + 1) + C], (idx == INT_MAX) ? -1.0 : (double)idx);
     }
     if (idx != INT_MAX) {
       const int lr = (int)(idx - r0);
       for (int e = t; e < Q * kb; e += PNT) {
         const int q = e / kb, c = e % kb;
-        cand[((size_t)g * Q + q) * kb + c] = sA[((size_t)c * Q + q) * R + lr];
+        put(&cand[((size_t)g * Q + q) * kb + c], SA(c, q, lr));
       }
     }
     if (k >= r0 && k < r0 + nr) {
       const int lr = (int)(k - r0);
       for (int e = t; e < Q * kb; e += PNT) {
         const int q = e / kb, c = e % kb;
-        rowk[q * kb + c] = sA[((size_t)c * Q + q) * R + lr];
+        put(&rowk[q * kb + c], SA(c, q, lr));
       }
     }
-    grid_sync(a.w.bar, (unsigned)G, gen);
+    grid_arrive(a.w.bar, (unsigned)G, (unsigned)k);
 
-    // (3) global winner
+    // (3) while the barrier is in flight: the pending step k-1 update of columns > k
+    if (!prev_zero && k + 1 < kb) {
+      const int lo = (int)(k - r0 > 0 ? k - r0 : 0);  // rows with local index >= k
+      const int cnt = nr - lo;
+      const int ncol = kb - k - 1;
+      for (int e = t; e < cnt * ncol; e += PNT) {
+        const int r = lo + e % cnt;
+        const int c = k + 1 + e / cnt;
+        double xr[C], xi[C], lr_[C], li[C], ur[C], ui[C];
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          xr[cc] = SA(c, cc, r);
+          xi[cc] = SA(c, C + cc, r);
+          lr_[cc] = SA(k - 1, cc, r);
+          li[cc] = SA(k - 1, C + cc, r);
+          ur[cc] = sPrev[cc * kb + c];
+          ui[cc] = sPrev[(C + cc) * kb + c];
+        }
+        mp::zfms<C>(xr, xi, lr_, li, ur, ui, xr, xi);
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          SA(c, cc, r) = xr[cc];
+          SA(c, C + cc, r) = xi[cc];
+        }
+      }
+    }
+    grid_wait(a.w.bar, (unsigned)k);
+
+    // (4) global winner
     double bv[C];
     int bi = INT_MAX;
 #pragma unroll
     for (int c = 0; c < C; ++c) bv[c] = 0.0;
     if (t < G) {
-      const double ix = part[t * (C + 1) + C];
+      const double ix = get(&part[t * (C + 1) + C]);
       if (ix >= 0.0) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) bv[c] = part[t * (C + 1) + c];
+        for (int c = 0; c < C; ++c) bv[c] = get(&part[t * (C + 1) + c]);
         bi = (int)ix;
       }
     }
@@ -272,8 +323,32 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     const int p = bi;
     const int gp = p / R;
     for (int e = t; e < Q * kb; e += PNT) {
-      sPiv[e] = cand[(size_t)gp * Q * kb + e];
-      sRowK[e] = rowk[e];
+      sPiv[e] = get(&cand[(size_t)gp * Q * kb + e]);
+      sRowK[e] = get(&rowk[e]);
+    }
+    __syncthreads();
+    // complete the two published rows with the pending step k-1 update
+    if (!prev_zero) {
+      for (int e = t; e < 2 * (kb - k - 1); e += PNT) {
+        double *row = (e & 1) ? sRowK : sPiv;
+        const int c = k + 1 + (e >> 1);
+        double xr[C], xi[C], lr_[C], li[C], ur[C], ui[C];
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          xr[cc] = row[cc * kb + c];
+          xi[cc] = row[(C + cc) * kb + c];
+          lr_[cc] = row[cc * kb + k - 1];
+          li[cc] = row[(C + cc) * kb + k - 1];
+          ur[cc] = sPrev[cc * kb + c];
+          ui[cc] = sPrev[(C + cc) * kb + c];
+        }
+        mp::zfms<C>(xr, xi, lr_, li, ur, ui, xr, xi);
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          row[cc * kb + c] = xr[cc];
+          row[(C + cc) * kb + c] = xi[cc];
+        }
+      }
     }
     bool zero = true;
 #pragma unroll
@@ -288,24 +363,21 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     __syncthreads();
 
     if (!zero) {
-      // (4) interchange rows k and p inside this workgroup's rows
+      // (5) interchange rows k and p inside this workgroup's rows
       if (p != k) {
         if (p >= r0 && p < r0 + nr) {
           const int lr = (int)(p - r0);
-          for (int e = t; e < Q * kb; e += PNT) {
-            const int q = e / kb, c = e % kb;
-            sA[((size_t)c * Q + q) * R + lr] = sRowK[e];
-          }
+          for (int e = t; e < Q * kb; e += PNT) SA(e % kb, e / kb, lr) = sRowK[e];
         }
         if (k >= r0 && k < r0 + nr) {
           const int lr = (int)(k - r0);
-          for (int e = t; e < Q * kb; e += PNT) {
-            const int q = e / kb, c = e % kb;
-            sA[((size_t)c * Q + q) * R + lr] = sPiv[e];
-          }
+          for (int e = t; e < Q * kb; e += PNT) SA(e % kb, e / kb, lr) = sPiv[e];
         }
+      } else if (k >= r0 && k < r0 + nr) {
+        const int lr = (int)(k - r0);
+        for (int e = t; e < Q * kb; e += PNT) SA(e % kb, e / kb, lr) = sPiv[e];
       }
-      // (5) reciprocal of the pivot
+      // (6) reciprocal of the pivot
       if (t == 0) {
         double pr[C], pi[C], rr[C], ri[C];
 #pragma unroll
@@ -321,58 +393,49 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
         }
       }
       __syncthreads();
-      // (6) multipliers l_i = a_ik / a_kk for rows below k
+      // (7) multipliers of column k, then column k+1 brought up to step k
       if (t < nr && r0 + t > k) {
         double xr[C], xi[C], rr[C], ri[C], lr_[C], li[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          xr[c] = sA[((size_t)k * Q + c) * R + t];
-          xi[c] = sA[((size_t)k * Q + C + c) * R + t];
+          xr[c] = SA(k, c, t);
+          xi[c] = SA(k, C + c, t);
           rr[c] = sRcp[c];
           ri[c] = sRcp[C + c];
         }
         mp::zmul<C>(xr, xi, rr, ri, lr_, li);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          sA[((size_t)k * Q + c) * R + t] = lr_[c];
-          sA[((size_t)k * Q + C + c) * R + t] = li[c];
+          SA(k, c, t) = lr_[c];
+          SA(k, C + c, t) = li[c];
         }
-      }
-      __syncthreads();
-      // (7) rank-1 update of this workgroup's rows below k, columns right of k
-      const int lo = (int)(k + 1 - r0 > 0 ? k + 1 - r0 : 0);
-      const int cnt = nr - lo;
-      const int ncol = kb - k - 1;
-      if (cnt > 0 && ncol > 0) {
-        for (int e = t; e < cnt * ncol; e += PNT) {
-          const int r = lo + e % cnt;
-          const int c = k + 1 + e / cnt;
-          double xr[C], xi[C], lr_[C], li[C], ur[C], ui[C];
+        if (k + 1 < kb) {
+          double ur[C], ui[C];
 #pragma unroll
-          for (int cc = 0; cc < C; ++cc) {
-            xr[cc] = sA[((size_t)c * Q + cc) * R + r];
-            xi[cc] = sA[((size_t)c * Q + C + cc) * R + r];
-            lr_[cc] = sA[((size_t)k * Q + cc) * R + r];
-            li[cc] = sA[((size_t)k * Q + C + cc) * R + r];
-            ur[cc] = sPiv[cc * kb + c];
-            ui[cc] = sPiv[(C + cc) * kb + c];
+          for (int c = 0; c < C; ++c) {
+            xr[c] = SA(k + 1, c, t);
+            xi[c] = SA(k + 1, C + c, t);
+            ur[c] = sPiv[c * kb + k + 1];
+            ui[c] = sPiv[(C + c) * kb + k + 1];
           }
           mp::zfms<C>(xr, xi, lr_, li, ur, ui, xr, xi);
 #pragma unroll
-          for (int cc = 0; cc < C; ++cc) {
-            sA[((size_t)c * Q + cc) * R + r] = xr[cc];
-            sA[((size_t)c * Q + C + cc) * R + r] = xi[cc];
+          for (int c = 0; c < C; ++c) {
+            SA(k + 1, c, t) = xr[c];
+            SA(k + 1, C + c, t) = xi[c];
           }
         }
       }
     }
+    // U row k becomes the previous row for the next iteration's pending update
+    for (int e = t; e < Q * kb; e += PNT) sPrev[e] = sPiv[e];
+    prev_zero = zero;
     __syncthreads();
   }
 
-  // write this workgroup's rows back
   for (int e = t; e < nr * kb * Q; e += PNT) {
     const int r = e % nr, rest = e / nr, c = rest % kb, q = rest / kb;
-    A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)] = sA[((size_t)c * Q + q) * R + r];
+    A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)] = SA(c, q, r);
   }
 
   // workgroup 0: the interchange list for the columns outside the panel.  Replaying the
@@ -423,10 +486,11 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
         }
       a.w.swl[0] = cntl;
       if (__hip_atomic_load(&a.w.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
-        *a.info = -9999;
+        *a.info = MPLU_SYNC_TIMEOUT;
     }
   }
 }
+#undef SA
 
 template <int C>
 __global__ __launch_bounds__(256) void k_laswp(ZM A, int64_t c0, int64_t c1, int64_t n,
