@@ -51,12 +51,30 @@ int getrs_ws(int C, int64_t n, int64_t nrhs, size_t *bytes) {
   return 0;
 }
 
+inline bool is_split(int method) {
+  return method == MPLU_GEMM_SPLIT_F64 || method == MPLU_GEMM_SPLIT_I8;
+}
+
+// slice options: n_slices 0 = default; slice_bits 0 or the fixed digit width (7 for INT8,
+// 22 for FP64)
+inline bool split_opts_ok(int C, int method, const mplu_opts_t *o) {
+  if (!is_split(method)) return true;
+  const bool i8 = method == MPLU_GEMM_SPLIT_I8;
+  const int S = o ? o->n_slices : 0;
+  const int w = o ? o->slice_bits : 0;
+  if (w != 0 && w != (i8 ? 7 : 22)) return false;
+  return split_supported(C, i8, S);
+}
+
 int getrf_ws(int C, int64_t m, int64_t n, const mplu_opts_t *o, size_t *bytes) {
   const int64_t mn = m < n ? m : n;
   int kb = panel_width(o);
   if (mn > 0 && kb > mn) kb = (int)mn;
   if (kb < 1) kb = 1;
-  *bytes = panel_ws_bytes(C, kb);
+  *bytes = align256(panel_ws_bytes(C, kb));
+  const int method = gemm_method(o);
+  if (is_split(method))
+    *bytes += split_ws_bytes(C, method == MPLU_GEMM_SPLIT_I8, m, n, kb, o ? o->n_slices : 0);
   return 0;
 }
 
@@ -123,7 +141,7 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M && method != MPLU_GEMM_SPLIT_F64 &&
       method != MPLU_GEMM_SPLIT_I8)
     return -7;
-  if (method == MPLU_GEMM_SPLIT_F64 || method == MPLU_GEMM_SPLIT_I8) return MPLU_E_UNSUPPORTED;
+  if (!split_opts_ok(prec, method, opts)) return MPLU_E_UNSUPPORTED;
   size_t need = 0;
   getrf_ws(prec, m, n, opts, &need);
   if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
@@ -139,15 +157,22 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   }
   HIPCHK(launch_fill_i32(d_info, 0, 1, s));
   const ZM a = zm(A);
+  void *split_ws = (char *)d_work + align256(panel_ws_bytes(C, kb));
   for (int64_t j = 0; j < mn; j += kb) {
     const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
     HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, d_work, s));
     HIPCHK(launch_laswp(C, a, j, j + jb, n, d_work, jb, s));
     if (j + jb < n) {
       HIPCHK(launch_trsm(C, true, true, false, a, j, jb, a, j, j + jb, n - j - jb, s));
-      if (j + jb < m)
-        HIPCHK(launch_gemm(C, method == MPLU_GEMM_3M ? 1 : 0, 'N', 'N', m - j - jb, n - j - jb,
-                           jb, -1, a, j + jb, j, a, j, j + jb, 1, a, j + jb, j + jb, s));
+      if (j + jb < m) {
+        if (is_split(method))
+          HIPCHK(launch_gemm_split(C, method == MPLU_GEMM_SPLIT_I8, opts ? opts->n_slices : 0,
+                                   'N', 'N', m - j - jb, n - j - jb, jb, -1, a, j + jb, j, a, j,
+                                   j + jb, 1, a, j + jb, j + jb, split_ws, s));
+        else
+          HIPCHK(launch_gemm(C, method == MPLU_GEMM_3M ? 1 : 0, 'N', 'N', m - j - jb, n - j - jb,
+                             jb, -1, a, j + jb, j, a, j, j + jb, 1, a, j + jb, j + jb, s));
+      }
     }
   }
   return 0;
@@ -262,23 +287,21 @@ int mplu_zgesv(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv
 
 int mplu_zgemm_wsbytes(int prec, int64_t m, int64_t n, int64_t k, int method,
                        const mplu_opts_t *opts, size_t *bytes) {
-  (void)opts;
   if (!prec_ok(prec)) return -1;
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (k < 0) return -4;
   if (method < 0 || method > 3) return -5;
   if (!bytes) return -7;
-  *bytes = 0;
+  *bytes = is_split(method) ? split_ws_bytes(prec, method == MPLU_GEMM_SPLIT_I8, m, n, k,
+                                             opts ? opts->n_slices : 0)
+                            : 0;
   return 0;
 }
 
 int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, int alpha_sign,
                mplu_zmat_t A, mplu_zmat_t B, int beta, mplu_zmat_t Cm, int method,
                const mplu_opts_t *opts, void *d_work, size_t work_bytes, void *stream) {
-  (void)opts;
-  (void)d_work;
-  (void)work_bytes;
   if (!prec_ok(prec)) return -1;
   if (opA != 'N' && opA != 'T' && opA != 'C') return -2;
   if (opB != 'N' && opB != 'T' && opB != 'C') return -3;
@@ -291,7 +314,18 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, in
   if (beta != 0 && beta != 1) return -10;
   if (!mat_ok(Cm, m, n)) return -11;
   if (method < 0 || method > 3) return -12;
-  if (method >= 2) return MPLU_E_UNSUPPORTED;
+  if (opts && opts->flags != 0) return -13;
+  if (is_split(method)) {
+    if (!split_opts_ok(prec, method, opts)) return MPLU_E_UNSUPPORTED;
+    size_t need = 0;
+    mplu_zgemm_wsbytes(prec, m, n, k, method, opts, &need);
+    if (m > 0 && n > 0 && (d_work == nullptr || ((uintptr_t)d_work & 255u))) return -14;
+    if (work_bytes < need) return MPLU_E_WORKSPACE;
+    HIPCHK(launch_gemm_split(prec, method == MPLU_GEMM_SPLIT_I8, opts ? opts->n_slices : 0, opA,
+                             opB, m, n, k, alpha_sign, zm(A), 0, 0, zm(B), 0, 0, beta, zm(Cm), 0,
+                             0, d_work, (hipStream_t)stream));
+    return 0;
+  }
   HIPCHK(launch_gemm(prec, method == MPLU_GEMM_3M ? 1 : 0, opA, opB, m, n, k, alpha_sign, zm(A),
                      0, 0, zm(B), 0, 0, beta, zm(Cm), 0, 0, (hipStream_t)stream));
   return 0;

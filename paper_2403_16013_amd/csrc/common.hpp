@@ -76,6 +76,16 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
                        int alpha_sign, ZM A, int64_t ai, int64_t aj, ZM B, int64_t bi,
                        int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s);
 
+// split products (Ozaki scheme) for the 3M form: digits on INT8 (i8) or FP64 MFMA; S = 0
+// selects the default slice count
+int split_slices(int C, bool i8);
+bool split_supported(int C, bool i8, int S);
+size_t split_ws_bytes(int C, bool i8, int64_t m, int64_t n, int64_t K, int S);
+hipError_t launch_gemm_split(int C, bool i8, int S, char opA, char opB, int64_t m, int64_t n,
+                             int64_t k, int alpha, ZM A, int64_t ai, int64_t aj, ZM B,
+                             int64_t bi, int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj,
+                             void *ws, hipStream_t s);
+
 // getrs helpers: perm from ipiv (n entries), then gather / scatter rows of B
 hipError_t launch_perm(const int32_t *ipiv, int64_t n, int32_t *perm, hipStream_t s);
 hipError_t launch_gather_rows(int C, const int32_t *perm, int64_t n, int64_t nrhs, ZM B, ZM W,

@@ -12,6 +12,8 @@
 // T3 = (ReA+ImA)(ReB+ImB) apart over the whole K range and combines them in the
 // epilogue: Re = T1 - T2, Im = T3 - T1 - T2, added to Cm with a single rounding per part.
 // 4M accumulates straight into Cm's value (alpha folded into the staged A).
+#include <stdlib.h>
+
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -26,7 +28,7 @@ struct GemmArgs {
   int alpha, beta;
 };
 
-template <int C, bool M3, int BM, int BN, int BK, int TM, int TN>
+template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR>
 __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
   constexpr int NT = (BM / TM) * (BN / TN);
   constexpr int NV = M3 ? 3 : 2;
@@ -126,7 +128,7 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
     }
     __syncthreads();
 
-#pragma unroll 1
+#pragma unroll UNR
     for (int kk = 0; kk < BK; ++kk) {
       double a[NV][TM][C], b[NV][TN][C];
 #pragma unroll
@@ -209,12 +211,34 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
     }
 }
 
-template <int C, bool M3, int BM, int BN, int BK, int TM, int TN>
+template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR>
 static hipError_t go(const GemmArgs &a, hipStream_t s) {
   constexpr int NT = (BM / TM) * (BN / TN);
   const dim3 grid((unsigned)((a.n + BN - 1) / BN), (unsigned)((a.m + BM - 1) / BM));
-  hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN>), grid, dim3(NT), 0, s, a);
+  hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN, UNR>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
+}
+
+// tile configurations for double-double (index selectable through MPLU_GEMM_CFG while
+// tuning); the default is entry 0
+template <bool M3>
+static hipError_t go_dd(int cfg, const GemmArgs &a, hipStream_t s) {
+  switch (cfg) {
+    case 1: return go<2, M3, 64, 32, 8, 4, 2, 1>(a, s);
+    case 2: return go<2, M3, 64, 64, 8, 4, 4, 1>(a, s);
+    case 3: return go<2, M3, 32, 64, 8, 2, 4, 1>(a, s);
+    case 4: return go<2, M3, 32, 32, 8, 2, 2, 2>(a, s);
+    case 5: return go<2, M3, 64, 32, 8, 4, 2, 2>(a, s);
+    case 6: return go<2, M3, 64, 64, 16, 4, 2, 1>(a, s);
+    case 7: return go<2, M3, 64, 64, 8, 2, 2, 1>(a, s);
+    case 8: return go<2, M3, 32, 32, 16, 2, 2, 1>(a, s);
+    default: return go<2, M3, 32, 32, 8, 2, 2, 1>(a, s);
+  }
+}
+
+static int gemm_cfg() {
+  const char *e = getenv("MPLU_GEMM_CFG");
+  return e ? atoi(e) : 0;
 }
 
 hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,
@@ -229,9 +253,9 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
   a.alpha = alpha_sign; a.beta = beta;
   const bool m3 = (method == 1);
   switch (C) {
-    case 2: return m3 ? go<2, true, 32, 32, 8, 2, 2>(a, s) : go<2, false, 32, 32, 8, 2, 2>(a, s);
-    case 3: return m3 ? go<3, true, 32, 32, 8, 2, 2>(a, s) : go<3, false, 32, 32, 8, 2, 2>(a, s);
-    case 4: return m3 ? go<4, true, 32, 32, 8, 2, 2>(a, s) : go<4, false, 32, 32, 8, 2, 2>(a, s);
+    case 2: return m3 ? go_dd<true>(gemm_cfg(), a, s) : go_dd<false>(gemm_cfg(), a, s);
+    case 3: return m3 ? go<3, true, 32, 32, 8, 2, 2, 1>(a, s) : go<3, false, 32, 32, 8, 2, 2, 1>(a, s);
+    case 4: return m3 ? go<4, true, 32, 32, 8, 2, 2, 1>(a, s) : go<4, false, 32, 32, 8, 2, 2, 1>(a, s);
   }
   return hipErrorInvalidValue;
 }

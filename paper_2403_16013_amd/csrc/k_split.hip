@@ -1,0 +1,385 @@
+// k_split.hip -- error-free split products on the matrix cores (the Ozaki scheme used by
+// Kouya Sec. 2.3 for the multiple-precision matrix product), applied to the 3M complex
+// product of Eq. 3m_cemm:  Cm := beta Cm + alpha (T1 - T2) + i alpha (T3 - T1 - T2) with
+// T1 = ReX ReY, T2 = ImX ImY, T3 = (ReX + ImX)(ReY + ImY).
+//
+// Slicing: every vector v of a real operand (a row of op(A) or a column of op(B)) gets an
+// exponent tau_v with |x| < 2^(tau_v - 1) for all its entries, and each entry is written
+// as sum_{p=1..S} d_p 2^(tau_v - p W) + (dropped tail) with integer digits
+// |d_p| <= 2^(W-1) + 1, taken by round-to-nearest from the multi-component residual.
+// Digit products are exact: for INT8 (W = 7) the MFMA accumulates them exactly in INT32;
+// for FP64 (W = 22) each level's sum stays below 2^53 for K <= 128 and is exact in FP64.
+// All digit-pair products of one level l = p + q <= S + 1 share one accumulator, since
+// they carry the same weight 2^(tau_i + tau_j - l W).  The per-level sums are then scaled
+// (exact powers of two) and added into multi-component accumulators.
+#include <stdlib.h>
+
+#include <type_traits>
+
+#include "common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mplu {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ slicing
+struct SliceArgs {
+  ZM M;
+  int64_t i0, j0;
+  int trans;  // element (v, t) = trans ? M(i0 + t, j0 + v) : M(i0 + v, j0 + t)
+  int conj;   // negate the imaginary part
+  int64_t nvec, K, Kpad;
+  void *out;      // [3][S][nvec][Kpad] digits (int8 or double)
+  int32_t *tau;   // [3][nvec]
+};
+
+template <int C>
+__device__ __forceinline__ void slice_elem(const SliceArgs &a, int64_t v, int64_t t,
+                                           double (&x)[3][C]) {
+  double re[C], im[C];
+  if (a.trans) ld_z<C>(a.M, a.i0 + t, a.j0 + v, re, im);
+  else ld_z<C>(a.M, a.i0 + v, a.j0 + t, re, im);
+  if (a.conj) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) im[c] = -im[c];
+  }
+  mp::renorm<C>(re, x[0]);
+  mp::renorm<C>(im, x[1]);
+  mp::add<C>(x[0], x[1], x[2]);  // the rounded sum of Eq. 3m_cemm
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// one wave per vector
+template <int C, int W, int S, typename T>
+__global__ __launch_bounds__(256) void k_slice(SliceArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= a.nvec) return;
+  double mx[3] = {0.0, 0.0, 0.0};
+  for (int64_t t = lane; t < a.K; t += 64) {
+    double x[3][C];
+    slice_elem<C>(a, v, t, x);
+#pragma unroll
+    for (int o = 0; o < 3; ++o) mx[o] = fmax(mx[o], fabs(x[o][0]));
+  }
+  int tau[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    const double m = wave_max(mx[o]);
+    int e = 0;
+    if (m > 0.0) frexp(m, &e);  // m < 2^e, hence every entry (with its tail) < 2^e
+    tau[o] = m > 0.0 ? e + 1 : 0;
+    if (lane == 0) a.tau[o * a.nvec + v] = tau[o];
+  }
+  T *out = (T *)a.out;
+  for (int64_t t = lane; t < a.Kpad; t += 64) {
+    double x[3][C];
+    if (t < a.K) {
+      slice_elem<C>(a, v, t, x);
+    } else {
+#pragma unroll
+      for (int o = 0; o < 3; ++o)
+#pragma unroll
+        for (int c = 0; c < C; ++c) x[o][c] = 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      double r[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) r[c] = x[o][c];
+#pragma unroll
+      for (int p = 1; p <= S; ++p) {
+        const double dn = ldexp(1.0, tau[o] - p * W);   // grid
+        const double d = rint(ldexp(r[0], p * W - tau[o]));
+        r[0] = __builtin_fma(-d, dn, r[0]);  // exact: d*dn is r[0] rounded to the grid
+        // bring the residual's leading part back to r[0]
+#pragma unroll
+        for (int c = C - 1; c > 0; --c) {
+          double s, e;
+          mp::two_sum(r[c - 1], r[c], s, e);
+          r[c - 1] = s;
+          r[c] = e;
+        }
+        out[(((int64_t)o * S + (p - 1)) * a.nvec + v) * a.Kpad + t] = (T)d;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ products
+struct SplitArgs {
+  const void *xs, *ys;        // digit planes of op(A) (m vectors) and op(B) (n vectors)
+  const int32_t *tx, *ty;     // exponents [3][m], [3][n]
+  int64_t m, n, Kpad;
+  ZM Cm;
+  int64_t ci, cj;
+  int alpha, beta;
+};
+
+// weights of the three real products in the real / imaginary parts
+__device__ __forceinline__ void op_signs(int op, double &sr, double &si) {
+  sr = (op == 0) ? 1.0 : (op == 1 ? -1.0 : 0.0);
+  si = (op == 2) ? 1.0 : -1.0;
+}
+
+template <int C>
+__device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t nj,
+                                         double (&lr)[C], double (&li)[C]) {
+  if (mi >= g.m || nj >= g.n) return;
+  if (g.alpha < 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) { lr[c] = -lr[c]; li[c] = -li[c]; }
+  }
+  if (g.beta) {
+    double cr[C], cim[C];
+    ld_z<C>(g.Cm, g.ci + mi, g.cj + nj, cr, cim);
+    mp::push_mp<C>(lr, cr);
+    mp::push_mp<C>(li, cim);
+  }
+  double orr[C], oi[C];
+  mp::renorm<C>(lr, orr);
+  mp::renorm<C>(li, oi);
+  st_z<C>(g.Cm, g.ci + mi, g.cj + nj, orr, oi);
+}
+
+// INT8 digits, W = 7.  Workgroup: 4 waves, a 32 x 32 output tile; each wave a 16 x 16
+// block.  For each real product, each block of LB levels and each 64-deep k chunk the
+// wave keeps up to QB digit fragments of its columns in registers, streams the digit
+// fragments of its rows, and issues one MFMA per digit pair into the level accumulator of
+// that pair (all pairs of one level share it).  Level blocks bound the accumulator
+// registers; they partition the pairs, so no product is computed twice.
+template <int C, int S, int LB, int QB>
+__global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
+  constexpr int W = 7;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * 32 + 16 * (w >> 1);
+  const int64_t n0 = (int64_t)blockIdx.x * 32 + 16 * (w & 1);
+  const int64_t arow = m0 + (lane & 15), bcol = n0 + (lane & 15);
+  const int64_t koff = 16 * (lane >> 4);
+  const int8_t *xs = (const int8_t *)g.xs, *ys = (const int8_t *)g.ys;
+  double lr[4][C], li[4][C];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
+
+  for (int op = 0; op < 3; ++op) {
+    double sr, si;
+    op_signs(op, sr, si);
+    const int8_t *xo = xs + (int64_t)op * S * g.m * g.Kpad;
+    const int8_t *yo = ys + (int64_t)op * S * g.n * g.Kpad;
+#pragma unroll
+    for (int lb0 = 0; lb0 < S; lb0 += LB) {
+      const int lmax = (lb0 + LB < S ? lb0 + LB : S) - 1;  // highest level of this block
+      v4i acc[LB];
+#pragma unroll
+      for (int l = 0; l < LB; ++l) acc[l] = v4i{0, 0, 0, 0};
+      for (int64_t kc = 0; kc < g.Kpad; kc += 64) {
+#pragma unroll
+        for (int qb0 = 0; qb0 < S; qb0 += QB) {
+          if (qb0 > lmax) continue;
+          v4i b[QB];
+#pragma unroll
+          for (int q = 0; q < QB; ++q)
+            b[q] = (qb0 + q <= lmax && bcol < g.n)
+                       ? *(const v4i *)(yo + ((int64_t)(qb0 + q) * g.n + bcol) * g.Kpad + kc + koff)
+                       : v4i{0, 0, 0, 0};
+#pragma unroll
+          for (int p = 0; p <= lmax; ++p) {
+            // pairs (p, q) of this level block with q in this column block
+            const int qlo = (lb0 - p > qb0) ? lb0 - p : qb0;
+            const int qhi = (lmax - p < qb0 + QB - 1) ? lmax - p : qb0 + QB - 1;
+            if (qlo > qhi) continue;
+            const v4i a = (arow < g.m)
+                              ? *(const v4i *)(xo + ((int64_t)p * g.m + arow) * g.Kpad + kc + koff)
+                              : v4i{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < QB; ++q) {
+              const int l = p + qb0 + q;
+              if (qb0 + q >= qlo && qb0 + q <= qhi)
+                acc[l - lb0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[q], acc[l - lb0], 0, 0, 0);
+            }
+          }
+        }
+      }
+      // level l (0-based) carries weight 2^(tau_i + tau_j - (l + 2) W); four consecutive
+      // levels span at most 24 + 3 W bits, so their scaled sum is exact in binary64
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
+        const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
+                         (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
+#pragma unroll
+        for (int top = lmax; top >= lb0; top -= 4) {
+          const int lo = top - 3 < lb0 ? lb0 : top - 3;
+          double grp = 0.0;
+#pragma unroll
+          for (int l = top; l >= lo; --l)
+            grp = __builtin_fma((double)acc[l - lb0][e], ldexp(1.0, (lo - l) * W), grp);
+          grp = ldexp(grp, tsum - (lo + 2) * W);
+          if (sr != 0.0) mp::push<C>(lr[e], 0, sr * grp);
+          mp::push<C>(li[e], 0, si * grp);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) epilogue<C>(g, m0 + 4 * (lane >> 4) + e, bcol, lr[e], li[e]);
+}
+
+// FP64 digits, W = 22, K processed in blocks of 128 (the exactness limit of one level).
+// D layout of the 16x16x4 FP64 MFMA: element (4 e + lane/16, lane % 16) in register e.
+template <int C, int S>
+__global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
+  constexpr int W = 22;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * 32 + 16 * (w >> 1);
+  const int64_t n0 = (int64_t)blockIdx.x * 32 + 16 * (w & 1);
+  const int64_t arow = m0 + (lane & 15), bcol = n0 + (lane & 15);
+  const int64_t kl = lane >> 4;
+  const double *xs = (const double *)g.xs, *ys = (const double *)g.ys;
+  double lr[4][C], li[4][C];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
+
+  for (int op = 0; op < 3; ++op) {
+    double sr, si;
+    op_signs(op, sr, si);
+    for (int64_t kb = 0; kb < g.Kpad; kb += 128) {
+      const int64_t kend = (kb + 128 < g.Kpad) ? kb + 128 : g.Kpad;
+      v4d acc[S];
+#pragma unroll
+      for (int l = 0; l < S; ++l) acc[l] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int64_t k4 = kb; k4 < kend; k4 += 4) {
+        double b[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+          b[q] = (bcol < g.n) ? ys[(((int64_t)op * S + q) * g.n + bcol) * g.Kpad + k4 + kl] : 0.0;
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          const double a = (arow < g.m) ? xs[(((int64_t)op * S + p) * g.m + arow) * g.Kpad + k4 + kl] : 0.0;
+#pragma unroll
+          for (int q = 0; q < S - p; ++q)
+            acc[p + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[q], acc[p + q], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t mi = m0 + 4 * e + (lane >> 4), nj = bcol;
+        const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
+                         (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
+#pragma unroll
+        for (int l = S - 1; l >= 0; --l) {
+          const double v = ldexp(acc[l][e], tsum - (l + 2) * W);
+          if (sr != 0.0) mp::push<C>(lr[e], 0, sr * v);
+          mp::push<C>(li[e], 0, si * v);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) epilogue<C>(g, m0 + 4 * e + (lane >> 4), bcol, lr[e], li[e]);
+}
+
+// ------------------------------------------------------------------ host side
+static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int split_slices(int C, bool i8) {
+  if (i8) return C == 2 ? 17 : (C == 3 ? 24 : 32);
+  return C == 2 ? 6 : (C == 3 ? 9 : 11);
+}
+
+static inline int64_t kpad_of(int64_t K, bool i8) {
+  const int64_t q = i8 ? 64 : 4;
+  return ((K + q - 1) / q) * q;
+}
+
+size_t split_ws_bytes(int C, bool i8, int64_t m, int64_t n, int64_t K, int S) {
+  if (S <= 0) S = split_slices(C, i8);
+  const size_t el = i8 ? 1 : 8;
+  const int64_t Kp = kpad_of(K, i8);
+  size_t b = al256(el * 3 * (size_t)S * (size_t)m * (size_t)Kp);
+  b += al256(el * 3 * (size_t)S * (size_t)n * (size_t)Kp);
+  b += al256(sizeof(int32_t) * 3 * (size_t)m) + al256(sizeof(int32_t) * 3 * (size_t)n);
+  return b;
+}
+
+template <int C, int S, bool I8>
+static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int alpha, ZM A,
+                      int64_t ai, int64_t aj, ZM B, int64_t bi, int64_t bj, int beta, ZM Cm,
+                      int64_t ci, int64_t cj, void *ws, hipStream_t s) {
+  typedef typename std::conditional<I8, int8_t, double>::type T;
+  constexpr int W = I8 ? 7 : 22;
+  const int64_t Kp = kpad_of(k, I8);
+  char *p = (char *)ws;
+  SliceArgs sx, sy;
+  sx.M = A; sx.i0 = ai; sx.j0 = aj; sx.trans = (opA != 'N'); sx.conj = (opA == 'C');
+  sx.nvec = m; sx.K = k; sx.Kpad = Kp;
+  sx.out = p;
+  p += al256(sizeof(T) * 3 * (size_t)S * (size_t)m * (size_t)Kp);
+  sy.M = B; sy.i0 = bi; sy.j0 = bj; sy.trans = (opB == 'N'); sy.conj = (opB == 'C');
+  sy.nvec = n; sy.K = k; sy.Kpad = Kp;
+  sy.out = p;
+  p += al256(sizeof(T) * 3 * (size_t)S * (size_t)n * (size_t)Kp);
+  sx.tau = (int32_t *)p;
+  p += al256(sizeof(int32_t) * 3 * (size_t)m);
+  sy.tau = (int32_t *)p;
+  hipLaunchKernelGGL((k_slice<C, W, S, T>), dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, sx);
+  hipLaunchKernelGGL((k_slice<C, W, S, T>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, sy);
+  SplitArgs g;
+  g.xs = sx.out; g.ys = sy.out; g.tx = sx.tau; g.ty = sy.tau;
+  g.m = m; g.n = n; g.Kpad = Kp;
+  g.Cm = Cm; g.ci = ci; g.cj = cj; g.alpha = alpha; g.beta = beta;
+  const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+  if constexpr (I8) {
+    constexpr int BLK = S > 17 ? 16 : S;
+    hipLaunchKernelGGL((k_split_i8<C, S, BLK, BLK>), grid, dim3(256), 0, s, g);
+  } else {
+    hipLaunchKernelGGL((k_split_f64<C, S>), grid, dim3(256), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_split(int C, bool i8, int S, char opA, char opB, int64_t m, int64_t n,
+                             int64_t k, int alpha, ZM A, int64_t ai, int64_t aj, ZM B,
+                             int64_t bi, int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj,
+                             void *ws, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (S <= 0) S = split_slices(C, i8);
+#define RUN(CC, SS, II) return run<CC, SS, II>(opA, opB, m, n, k, alpha, A, ai, aj, B, bi, bj, beta, Cm, ci, cj, ws, s)
+  if (i8) {
+    if (C == 2 && S == 17) RUN(2, 17, true);
+    if (C == 3 && S == 24) RUN(3, 24, true);
+    if (C == 4 && S == 32) RUN(4, 32, true);
+  } else {
+    if (C == 2) {
+      if (S == 3) RUN(2, 3, false);
+      if (S == 4) RUN(2, 4, false);
+      if (S == 5) RUN(2, 5, false);
+      if (S == 6) RUN(2, 6, false);
+    }
+    if (C == 3 && S == 9) RUN(3, 9, false);
+    if (C == 4 && S == 11) RUN(4, 11, false);
+  }
+#undef RUN
+  return hipErrorInvalidValue;
+}
+
+bool split_supported(int C, bool i8, int S) {
+  if (S <= 0) return true;
+  if (i8) return S == split_slices(C, true);
+  if (C == 2) return S >= 3 && S <= 6;
+  return S == split_slices(C, false);
+}
+
+}  // namespace mplu

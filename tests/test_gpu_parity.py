@@ -234,3 +234,87 @@ def test_deterministic(mp, orc, method):
         sync()
         outs.append((to_host(T), ipiv.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+# ---------------------------------------------------------------- split (Ozaki) products
+SPLIT = ["split_i8", "split_f64"]
+
+
+def split_tol(A, B, Cm, opA, opB, C, k):
+    """gemm_tol plus the slicing term k 2^-(53C+2) max_t|a_it| max_t|b_tj| (digits cover
+    53C+2 bits below each row / column maximum)."""
+    from helpers import cabs1_hi
+
+    a = cabs1_hi(A)
+    b = cabs1_hi(B)
+    if opA != "N":
+        a = a.T
+    if opB != "N":
+        b = b.T
+    mx = np.outer(a.max(axis=1), b.max(axis=0))
+    return gemm_tol(A, B, Cm, opA, opB, C, k) + 4 * k * 2.0 ** (-53 * C - 2) * mx * 4
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", SPLIT)
+@pytest.mark.parametrize("ops", [("N", "N"), ("C", "T")])
+def test_split_gemm_vs_oracle(mp, orc, C, method, ops):
+    opA, opB = ops
+    m, n, k = 70, 45, 150
+    A = orc.canon(synthgen.uniform(m if opA == "N" else k, k if opA == "N" else m, C, 90))
+    B = orc.canon(synthgen.uniform(k if opB == "N" else n, n if opB == "N" else k, C, 91))
+    Cm = orc.canon(synthgen.uniform(m, n, C, 92))
+    ref = orc.gemm(A, B, Cm, method=3, opA=opA, opB=opB, alpha_sign=-1)
+    Td = to_dev(Cm)
+    mp.gemm(to_dev(A), to_dev(B), Td, opA=opA, opB=opB, alpha=-1, method=method)
+    d = orc.diff(to_host(Td), ref)
+    tol = split_tol(A, B, Cm, opA, opB, C, k)
+    assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", SPLIT)
+def test_split_gemm_exact_on_dyadic_data(mp, C, method):
+    """Pin P9: on small dyadic data every digit product is exact, so the split product
+    equals the exact complex product bit for bit."""
+    rng = np.random.default_rng(6)
+    m, n, k = 67, 41, 130
+    Ac = (rng.integers(-99, 100, (m, k)) + 1j * rng.integers(-99, 100, (m, k))) / 8
+    Bc = (rng.integers(-99, 100, (k, n)) + 1j * rng.integers(-99, 100, (k, n))) / 8
+    Cc = (rng.integers(-99, 100, (m, n)) + 1j * rng.integers(-99, 100, (m, n))) / 8
+    Td = to_dev(synthgen.planes_from_complex(Cc, C))
+    mp.gemm(to_dev(synthgen.planes_from_complex(Ac, C)), to_dev(synthgen.planes_from_complex(Bc, C)),
+            Td, alpha=-1, method=method)
+    got = to_host(Td)
+    assert np.array_equal((got[0, 0] + 1j * got[1, 0]).T, Cc - Ac @ Bc)
+    assert not np.any(got[:, 1:])
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", SPLIT)
+def test_getrf_split_vs_oracle(mp, orc, C, method):
+    A, LUg, ipg, LUo, ipo = _lu_parity(mp, orc, C, 200, 64, method, 35 + C)
+    xt = synthgen.ones(200, 1, C)
+    b = orc.matmul_exact(A, xt)
+    Bd = to_dev(b)
+    T = to_dev(LUg)
+    mp.getrs(T, __import__("torch").from_numpy(ipg).cuda(), Bd)
+    eta = orc.backward_error(A, to_host(Bd), b)
+    assert eta <= 10 * 200 * U_FMT[C]
+
+
+@pytest.mark.parametrize("S", [3, 4, 5, 6])
+def test_split_f64_slice_count_sweep(mp, orc, S):
+    """The division-count sweep of the paper's Ozaki LU (DD): fewer FP64 slices give a
+    larger backward error; the default (6) meets the bound."""
+    n = 160
+    A = orc.canon(synthgen.uniform(n, n, 2, 44))
+    b = orc.matmul_exact(A, synthgen.ones(n, 1, 2))
+    T, Bd = to_dev(A), to_dev(b)
+    mp.gesv(T, Bd, panel=32, method="split_f64", n_slices=S)
+    sync()
+    eta = orc.backward_error(A, to_host(Bd), b)
+    if S == 6:
+        assert eta <= 10 * n * U_FMT[2]
+    else:
+        assert eta < 1e-8
