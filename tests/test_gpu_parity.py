@@ -161,7 +161,7 @@ def test_getrs_vs_oracle(mp, orc, C, trans):
     Bd = to_dev(B)
     mp.getrs(T, ipiv, Bd, trans=trans)
     Xg = to_host(Bd)
-    kappa = np.linalg.cond(orc.hi_complex(A), np.inf)
+    kappa = float(np.real(np.linalg.cond(orc.hi_complex(A), np.inf)))
     d = orc.diff(Xg, Xo)
     assert np.abs(d).max() / np.abs(orc.hi_complex(Xo)).max() <= 10 * n * kappa * U_FMT[C]
     if trans == "C":

@@ -216,7 +216,7 @@ def test_solve_vs_mpmath_1024_bits(orc, C):
             xi = sum(mpmath.mpf(float(v)) for v in x[1, :, 0, i])
             errs.append(float(abs(mpmath.mpc(xr, xi) - xm[i])))
             mags.append(float(abs(xm[i])))
-    kappa = np.linalg.cond(orc.hi_complex(A), np.inf)
+    kappa = float(np.real(np.linalg.cond(orc.hi_complex(A), np.inf)))
     assert max(errs) / max(mags) <= 10 * n * kappa * U_FMT[C]
 
 
