@@ -49,6 +49,9 @@ def parse():
     p.add_argument("--no-roofline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target length of the CPU oracle sample")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="first run one plain 1 GiB device-to-device copy (a reference for "
+                        "hardware memory counters)")
     return p.parse_args()
 
 
@@ -157,11 +160,27 @@ def gemm_roofline(mp, torch, A0, panel, method):
         "peak": PEAK_FP64_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-        "traffic": None,
+        "traffic": committed_traffic("k_gemm.hip") if (C, method) == (2, "3m") else None,
         "launches": len(launches),
         "avg_launch_ms": round(total_ms / len(launches), 4),
         "flops_per_launch": flops / len(launches),
     }
+
+
+def committed_traffic(kernel_src):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, or None when that kernel's source changed after the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "gemm_dd_3m_n4096_counters.txt")
+    src = os.path.join(ROOT, "paper_2403_16013_amd", "csrc", kernel_src)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != h:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(synthgen, n, target_s):
@@ -198,6 +217,13 @@ def main():
     import synthgen
 
     n, panel, method = args.n, args.panel, args.method
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] DD n={n} panel={panel} {method}: building inputs", file=sys.stderr,
           flush=True)
     A0, B0 = make_problem(mp, torch, synthgen, n, 2)
@@ -230,17 +256,24 @@ def main():
         print(f"[bench] roofline {line['roofline']}", file=sys.stderr, flush=True)
     if not args.no_variants:
         var = {}
-        for (C, meth, pnl, steps) in ((2, "4m", panel, 2), (2, "3m", 128, 2), (3, "3m", panel, 1),
-                                      (4, "3m", panel, 1)):
-            A, B = (A0, B0) if C == 2 else make_problem(mp, torch, synthgen, n, C)
+        runs = ((2, "4m", panel, 2), (2, "3m", 128, 2), (2, "split_i8", 128, 2),
+                (2, "split_f64", 128, 1), (3, "3m", panel, 1), (3, "split_i8", 128, 1),
+                (4, "3m", panel, 1), (4, "split_i8", 128, 1))
+        probs = {2: (A0, B0)}
+        for (C, meth, pnl, steps) in runs:
+            if C not in probs:
+                probs = {2: (A0, B0), C: make_problem(mp, torch, synthgen, n, C)}
+                torch.cuda.empty_cache()
+            A, B = probs[C]
             vms, _, VX, vinfo = time_gesv(mp, torch, A, B, steps, 1, pnl, meth)
             veta = backward_error(mp, torch, A, VX, B)
             key = f"{['', '', 'DD', 'TD', 'QD'][C]}_{meth}_K{pnl}"
             var[key] = {"ms": round(vms, 3), "gflops": round(eff_gflops(n, vms / 1e3), 2),
                         "eta": veta, "info": vinfo}
             print(f"[bench] variant {key}: {var[key]}", file=sys.stderr, flush=True)
-            del A, B, VX
+            del VX
             torch.cuda.empty_cache()
+        del probs
         line["variants"] = var
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
