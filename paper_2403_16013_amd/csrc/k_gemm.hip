@@ -211,6 +211,83 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
     }
 }
 
+// Narrow products (n <= 16 output columns, 4M): the block updates of the forward and
+// backward substitutions.  One thread per output element; op(B) is staged in LDS in
+// 32-deep chunks, op(A) is read straight from global memory (each row by n neighbouring
+// threads).  Accumulation is the same 4M level accumulation as k_gemm.
+template <int C>
+__global__ __launch_bounds__(256) void k_gemm_narrow(GemmArgs g, int npow) {
+  constexpr int KC = 32;
+  __shared__ double sB[KC][2][C][16];
+  const int t = threadIdx.x;
+  const int rows_per_block = 256 / npow;
+  const int64_t mi = (int64_t)blockIdx.x * rows_per_block + t / npow;
+  const int nj = t % npow;
+  const bool live = (mi < g.m) && (nj < g.n);
+  double acr[C], aci[C];
+  mp::set_zero<C>(acr);
+  mp::set_zero<C>(aci);
+  if (live && g.beta) ld_z<C>(g.Cm, g.ci + mi, g.cj + nj, acr, aci);
+  const double asign = g.alpha < 0 ? -1.0 : 1.0;
+  for (int64_t k0 = 0; k0 < g.k; k0 += KC) {
+    __syncthreads();
+    for (int e = t; e < KC * 16; e += 256) {
+      const int kk = e % KC, jj = e / KC;
+      double re[C], im[C];
+      if (k0 + kk < g.k && jj < g.n) {
+        if (g.opB == 'N') ld_z<C>(g.B, g.bi + k0 + kk, g.bj + jj, re, im);
+        else ld_z<C>(g.B, g.bi + jj, g.bj + k0 + kk, re, im);
+        if (g.opB == 'C') {
+#pragma unroll
+          for (int c = 0; c < C; ++c) im[c] = -im[c];
+        }
+      } else {
+        mp::set_zero<C>(re);
+        mp::set_zero<C>(im);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) { sB[kk][0][c][jj] = re[c]; sB[kk][1][c][jj] = im[c]; }
+    }
+    __syncthreads();
+    if (!live) continue;
+    const int kend = (g.k - k0 < KC) ? (int)(g.k - k0) : KC;
+    for (int kk = 0; kk < kend; ++kk) {
+      double ar[C], ai[C], nai[C], br[C], bi[C];
+      if (g.opA == 'N') ld_z<C>(g.A, g.ai + mi, g.aj + k0 + kk, ar, ai);
+      else ld_z<C>(g.A, g.ai + k0 + kk, g.aj + mi, ar, ai);
+      const double isg = (g.opA == 'C') ? -asign : asign;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        ar[c] *= asign;
+        ai[c] *= isg;
+        nai[c] = -ai[c];
+        br[c] = sB[kk][0][c][nj];
+        bi[c] = sB[kk][1][c][nj];
+      }
+      mp::mac<C>(acr, ar, br);
+      mp::mac<C>(acr, nai, bi);
+      mp::mac<C>(aci, ar, bi);
+      mp::mac<C>(aci, ai, br);
+    }
+  }
+  if (live) {
+    double ore[C], oim[C];
+    mp::renorm<C>(acr, ore);
+    mp::renorm<C>(aci, oim);
+    st_z<C>(g.Cm, g.ci + mi, g.cj + nj, ore, oim);
+  }
+}
+
+template <int C>
+static hipError_t go_narrow(const GemmArgs &a, hipStream_t s) {
+  int npow = 1;
+  while (npow < a.n) npow <<= 1;
+  const int rows_per_block = 256 / npow;
+  const int64_t blocks = (a.m + rows_per_block - 1) / rows_per_block;
+  hipLaunchKernelGGL((k_gemm_narrow<C>), dim3((unsigned)blocks), dim3(256), 0, s, a, npow);
+  return hipGetLastError();
+}
+
 template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR>
 static hipError_t go(const GemmArgs &a, hipStream_t s) {
   constexpr int NT = (BM / TM) * (BN / TN);
@@ -252,6 +329,14 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
   a.opA = opA; a.opB = opB;
   a.alpha = alpha_sign; a.beta = beta;
   const bool m3 = (method == 1);
+  if (!m3 && n <= 16) {
+    switch (C) {
+      case 2: return go_narrow<2>(a, s);
+      case 3: return go_narrow<3>(a, s);
+      case 4: return go_narrow<4>(a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (C) {
     case 2: return m3 ? go_dd<true>(gemm_cfg(), a, s) : go_dd<false>(gemm_cfg(), a, s);
     case 3: return m3 ? go<3, true, 32, 32, 8, 2, 2, 1>(a, s) : go<3, false, 32, 32, 8, 2, 2, 1>(a, s);

@@ -151,19 +151,22 @@ __device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t
 }
 
 // INT8 digits, W = 7.  Workgroup: 4 waves, a 32 x 32 output tile; each wave a 16 x 16
-// block.  For each real product, each block of LB levels and each 64-deep k chunk the
-// wave keeps up to QB digit fragments of its columns in registers, streams the digit
-// fragments of its rows, and issues one MFMA per digit pair into the level accumulator of
-// that pair (all pairs of one level share it).  Level blocks bound the accumulator
-// registers; they partition the pairs, so no product is computed twice.
-template <int C, int S, int LB, int QB>
+// block.  For each real product and each 64-deep k chunk the workgroup stages the S digit
+// planes of its 32 rows and 32 columns in LDS (16-byte coalesced loads, shared by the four
+// waves); each wave then holds the S row fragments and S column fragments of its block in
+// registers and issues one MFMA per digit pair p + q <= S - 1 (0-based) into the level
+// accumulator of that pair: all pairs of one level share it.
+template <int C, int S>
 __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   constexpr int W = 7;
+  extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes]
+  v4i *sX = sdig, *sY = sdig + S * 32 * 4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t m0 = (int64_t)blockIdx.y * 32 + 16 * (w >> 1);
-  const int64_t n0 = (int64_t)blockIdx.x * 32 + 16 * (w & 1);
-  const int64_t arow = m0 + (lane & 15), bcol = n0 + (lane & 15);
-  const int64_t koff = 16 * (lane >> 4);
+  const int64_t M0 = (int64_t)blockIdx.y * 32, N0 = (int64_t)blockIdx.x * 32;
+  const int64_t m0 = M0 + 16 * (w >> 1), n0 = N0 + 16 * (w & 1);
+  const int64_t bcol = n0 + (lane & 15);
+  const int frow = 16 * (w >> 1) + (lane & 15), fcol = 16 * (w & 1) + (lane & 15);
+  const int fk = lane >> 4;   // which 16-byte quarter of the 64-deep chunk
   const int8_t *xs = (const int8_t *)g.xs, *ys = (const int8_t *)g.ys;
   double lr[4][C], li[4][C];
 #pragma unroll
@@ -176,58 +179,50 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
     op_signs(op, sr, si);
     const int8_t *xo = xs + (int64_t)op * S * g.m * g.Kpad;
     const int8_t *yo = ys + (int64_t)op * S * g.n * g.Kpad;
+    v4i acc[S];
 #pragma unroll
-    for (int lb0 = 0; lb0 < S; lb0 += LB) {
-      const int lmax = (lb0 + LB < S ? lb0 + LB : S) - 1;  // highest level of this block
-      v4i acc[LB];
-#pragma unroll
-      for (int l = 0; l < LB; ++l) acc[l] = v4i{0, 0, 0, 0};
-      for (int64_t kc = 0; kc < g.Kpad; kc += 64) {
-#pragma unroll
-        for (int qb0 = 0; qb0 < S; qb0 += QB) {
-          if (qb0 > lmax) continue;
-          v4i b[QB];
-#pragma unroll
-          for (int q = 0; q < QB; ++q)
-            b[q] = (qb0 + q <= lmax && bcol < g.n)
-                       ? *(const v4i *)(yo + ((int64_t)(qb0 + q) * g.n + bcol) * g.Kpad + kc + koff)
-                       : v4i{0, 0, 0, 0};
-#pragma unroll
-          for (int p = 0; p <= lmax; ++p) {
-            // pairs (p, q) of this level block with q in this column block
-            const int qlo = (lb0 - p > qb0) ? lb0 - p : qb0;
-            const int qhi = (lmax - p < qb0 + QB - 1) ? lmax - p : qb0 + QB - 1;
-            if (qlo > qhi) continue;
-            const v4i a = (arow < g.m)
-                              ? *(const v4i *)(xo + ((int64_t)p * g.m + arow) * g.Kpad + kc + koff)
-                              : v4i{0, 0, 0, 0};
-#pragma unroll
-            for (int q = 0; q < QB; ++q) {
-              const int l = p + qb0 + q;
-              if (qb0 + q >= qlo && qb0 + q <= qhi)
-                acc[l - lb0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b[q], acc[l - lb0], 0, 0, 0);
-            }
-          }
-        }
+    for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
+    for (int64_t kc = 0; kc < g.Kpad; kc += 64) {
+      __syncthreads();
+      // stage: entry e = (plane p, row r, quarter f), 16 bytes each
+      for (int e = threadIdx.x; e < S * 32 * 4; e += 256) {
+        const int f = e & 3, r = (e >> 2) & 31, p = e >> 7;
+        const int64_t gi = M0 + r, gj = N0 + r;
+        sX[e] = (gi < g.m) ? *(const v4i *)(xo + ((int64_t)p * g.m + gi) * g.Kpad + kc + 16 * f)
+                           : v4i{0, 0, 0, 0};
+        sY[e] = (gj < g.n) ? *(const v4i *)(yo + ((int64_t)p * g.n + gj) * g.Kpad + kc + 16 * f)
+                           : v4i{0, 0, 0, 0};
       }
-      // level l (0-based) carries weight 2^(tau_i + tau_j - (l + 2) W); four consecutive
-      // levels span at most 24 + 3 W bits, so their scaled sum is exact in binary64
+      __syncthreads();
+      v4i a[S], b[S];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
-        const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
-                         (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
+      for (int p = 0; p < S; ++p) {
+        a[p] = sX[(p * 32 + frow) * 4 + fk];
+        b[p] = sY[(p * 32 + fcol) * 4 + fk];
+      }
 #pragma unroll
-        for (int top = lmax; top >= lb0; top -= 4) {
-          const int lo = top - 3 < lb0 ? lb0 : top - 3;
-          double grp = 0.0;
+      for (int p = 0; p < S; ++p)
 #pragma unroll
-          for (int l = top; l >= lo; --l)
-            grp = __builtin_fma((double)acc[l - lb0][e], ldexp(1.0, (lo - l) * W), grp);
-          grp = ldexp(grp, tsum - (lo + 2) * W);
-          if (sr != 0.0) mp::push<C>(lr[e], 0, sr * grp);
-          mp::push<C>(li[e], 0, si * grp);
-        }
+        for (int q = 0; q < S - p; ++q)
+          acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
+    }
+    // level l (0-based) carries weight 2^(tau_i + tau_j - (l + 2) W); four consecutive
+    // levels span at most 24 + 3 W bits, so their scaled sum is exact in binary64
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
+      const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
+                       (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
+#pragma unroll
+      for (int top = S - 1; top >= 0; top -= 4) {
+        const int lo = top - 3 < 0 ? 0 : top - 3;
+        double grp = 0.0;
+#pragma unroll
+        for (int l = top; l >= lo; --l)
+          grp = __builtin_fma((double)acc[l][e], ldexp(1.0, (lo - l) * W), grp);
+        grp = ldexp(grp, tsum - (lo + 2) * W);
+        if (sr != 0.0) mp::push<C>(lr[e], 0, sr * grp);
+        mp::push<C>(li[e], 0, si * grp);
       }
     }
   }
@@ -342,8 +337,15 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
   g.Cm = Cm; g.ci = ci; g.cj = cj; g.alpha = alpha; g.beta = beta;
   const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
   if constexpr (I8) {
-    constexpr int BLK = S > 17 ? 16 : S;
-    hipLaunchKernelGGL((k_split_i8<C, S, BLK, BLK>), grid, dim3(256), 0, s, g);
+    const size_t lds = sizeof(v4i) * 2 * S * 32 * 4;
+    static bool attr = false;
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute((const void *)k_split_i8<C, S>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_split_i8<C, S>), grid, dim3(256), lds, s, g);
   } else {
     hipLaunchKernelGGL((k_split_f64<C, S>), grid, dim3(256), 0, s, g);
   }

@@ -3,9 +3,10 @@
 //
 // Used for the block row of U in the blocked LU (U12 := L11^-1 A12, Kouya Sec. 3) and for
 // the diagonal blocks of the forward / backward substitutions (Sec. 4).  Each workgroup
-// owns a strip of columns of X held in LDS and sweeps the nb rows in order; the entries
-// of T are read from global memory (the block is small and stays in L2).  Element
-// operations use the 4M complex product with one rounding per part (Eq. 4m).
+// owns a strip of columns of X held in LDS, stages the triangle in LDS and sweeps the nb
+// rows in order.  Blocks whose triangle does not fit are split in halves around a 4M
+// product.  Element operations use the 4M complex product with one rounding per part
+// (Eq. 4m).
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -34,21 +35,50 @@ __device__ __forceinline__ void ld_opT(const TrsmArgs &a, int r, int i, double (
   }
 }
 
-// LOWER: op(T) is lower triangular (forward sweep); UNIT: unit diagonal
+// LOWER: op(T) is lower triangular (forward sweep); UNIT: unit diagonal.
+// The strict triangle of op(T) is staged once in LDS, packed by columns in component
+// planes (column i holds rows i+1..nb-1 when LOWER, rows 0..i-1 otherwise), so the sweep
+// reads it at LDS latency; the diagonal is kept as reciprocals.
 template <int C, bool LOWER, bool UNIT, bool CONJ>
 __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   extern __shared__ double smem[];
   constexpr int Q = 2 * C;
   const int nb = a.nb, NBC = a.nbc, t = threadIdx.x;
+  const int ntri = nb * (nb - 1) / 2;
   const int64_t cb = a.c0 + (int64_t)blockIdx.x * NBC;
   const int64_t left = a.c0 + a.ncols - cb;
   const int ncl = (int)(left < NBC ? left : NBC);
   double *sX = smem;                          // [nb][Q][NBC]
   double *sR = sX + (size_t)nb * Q * NBC;     // [nb][Q] reciprocals of the diagonal
+  double *sT = sR + (size_t)nb * Q;           // [Q][ntri] packed strict triangle
+
+  auto col_off = [&](int i) { return LOWER ? i * (nb - 1) - i * (i - 1) / 2 : i * (i - 1) / 2; };
 
   for (int e = t; e < nb * ncl * Q; e += 256) {
     const int r = e % nb, rest = e / nb, cc = rest % ncl, q = rest / ncl;
     sX[((size_t)r * Q + q) * NBC + cc] = a.X.p[(int64_t)q * a.X.ps + (cb + cc) * a.X.ld + a.x0 + r];
+  }
+  // strict triangle: enumerate (column i, row r) pairs column by column
+  for (int e = t; e < ntri; e += 256) {
+    int i, r;
+    if (LOWER) {  // column i has nb-1-i entries
+      i = 0;
+      int acc = 0;
+      while (acc + (nb - 1 - i) <= e) { acc += nb - 1 - i; ++i; }
+      r = i + 1 + (e - acc);
+    } else {      // column i has i entries
+      i = 1;
+      int acc = 0;
+      while (acc + i <= e) { acc += i; ++i; }
+      r = e - acc;
+    }
+    double tr[C], ti[C];
+    ld_opT<C, CONJ>(a, r, i, tr, ti);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      sT[(size_t)c * ntri + e] = tr[c];
+      sT[(size_t)(C + c) * ntri + e] = ti[c];
+    }
   }
   if (!UNIT) {
     for (int i = t; i < nb; i += 256) {
@@ -85,15 +115,16 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
       }
       __syncthreads();
     }
-    // rows still to be updated by x_i
     const int rlo = LOWER ? i + 1 : 0;
     const int rcnt = LOWER ? nb - i - 1 : i;
+    const int off = col_off(i);
     for (int e = t; e < rcnt * ncl; e += 256) {
       const int r = rlo + e / ncl, cc = e % ncl;
       double tr[C], ti[C], xr[C], xi[C], yr[C], yi[C];
-      ld_opT<C, CONJ>(a, r, i, tr, ti);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
+        tr[c] = sT[(size_t)c * ntri + off + (r - rlo)];
+        ti[c] = sT[(size_t)(C + c) * ntri + off + (r - rlo)];
         xr[c] = sX[((size_t)r * Q + c) * NBC + cc];
         xi[c] = sX[((size_t)r * Q + C + c) * NBC + cc];
         yr[c] = sX[((size_t)i * Q + c) * NBC + cc];
@@ -118,7 +149,8 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
 template <int C, bool LOWER, bool UNIT, bool CONJ>
 static hipError_t go(const TrsmArgs &a, hipStream_t s) {
   constexpr int Q = 2 * C;
-  const size_t lds = sizeof(double) * ((size_t)a.nb * Q * a.nbc + (size_t)a.nb * Q);
+  const size_t lds = sizeof(double) * ((size_t)a.nb * Q * a.nbc + (size_t)a.nb * Q +
+                                        (size_t)Q * (a.nb * (a.nb - 1) / 2));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void *)k_trsm<C, LOWER, UNIT, CONJ>,
@@ -143,10 +175,36 @@ static hipError_t dispatch(bool lower, bool unit, bool conj, const TrsmArgs &a, 
   return conj ? go<C, false, false, true>(a, s) : go<C, false, false, false>(a, s);
 }
 
+static inline size_t tri_fixed(int C, int nb) {
+  return sizeof(double) * 2 * C * ((size_t)nb + (size_t)nb * (nb - 1) / 2);
+}
+
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
                        ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s) {
   if (nb <= 0 || ncols <= 0) return hipSuccess;
-  if (nb > 128) return hipErrorInvalidValue;
+  if (tri_fixed(C, nb) + sizeof(double) * 2 * C * nb > 128 * 1024) {
+    // the packed triangle does not fit: split op(T) into halves,
+    //   lower op:  X1 = T11^-1 X1;  X2 -= T21 X1;  X2 = T22^-1 X2
+    //   upper op:  X2 = T22^-1 X2;  X1 -= T12 X2;  X1 = T11^-1 X1
+    const int h = nb / 2, r = nb - h;
+    const bool opl = lower != conj;
+    const char opA = conj ? 'C' : 'N';
+    hipError_t e;
+    if (opl) {
+      if ((e = launch_trsm(C, lower, unit, conj, Tm, t0, h, Xm, x0, c0, ncols, s)) != hipSuccess) return e;
+      // T21 = op(T)[h:, :h]: stored at (t0+h, t0) untransposed, else (t0, t0+h) transposed
+      if ((e = launch_gemm(C, 0, opA, 'N', r, ncols, h, -1, Tm, conj ? t0 : t0 + h,
+                           conj ? t0 + h : t0, Xm, x0, c0, 1, Xm, x0 + h, c0, s)) != hipSuccess)
+        return e;
+      return launch_trsm(C, lower, unit, conj, Tm, t0 + h, r, Xm, x0 + h, c0, ncols, s);
+    }
+    if ((e = launch_trsm(C, lower, unit, conj, Tm, t0 + h, r, Xm, x0 + h, c0, ncols, s)) != hipSuccess) return e;
+    // T12 = op(T)[:h, h:]: stored at (t0, t0+h) untransposed, else (t0+h, t0) transposed
+    if ((e = launch_gemm(C, 0, opA, 'N', h, ncols, r, -1, Tm, conj ? t0 + h : t0,
+                         conj ? t0 : t0 + h, Xm, x0 + h, c0, 1, Xm, x0, c0, s)) != hipSuccess)
+      return e;
+    return launch_trsm(C, lower, unit, conj, Tm, t0, h, Xm, x0, c0, ncols, s);
+  }
   TrsmArgs a;
   a.T = Tm;
   a.t0 = t0;
@@ -155,9 +213,11 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
   a.x0 = x0;
   a.c0 = c0;
   a.ncols = ncols;
-  // columns per workgroup: as many as 64 KB of LDS allows, at most 32
-  int nbc = 32;
-  while (nbc > 1 && sizeof(double) * (size_t)nb * 2 * C * nbc > 64 * 1024) nbc >>= 1;
+  // columns per workgroup: the packed triangle and the diagonal take their share of the
+  // LDS, the column strip the rest (at most 16 columns)
+  const size_t fixed = tri_fixed(C, nb);
+  int nbc = 16;
+  while (nbc > 1 && fixed + sizeof(double) * (size_t)nb * 2 * C * nbc > 160 * 1024) nbc >>= 1;
   a.nbc = nbc;
   switch (C) {
     case 2: return dispatch<2>(lower, unit, conj, a, s);

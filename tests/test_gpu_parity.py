@@ -318,3 +318,27 @@ def test_split_f64_slice_count_sweep(mp, orc, S):
         assert eta <= 10 * n * U_FMT[2]
     else:
         assert eta < 1e-8
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("ncols", [1, 3, 16])
+@pytest.mark.parametrize("opA", ["N", "C"])
+def test_narrow_gemm_vs_oracle(mp, orc, C, ncols, opA):
+    """Products with at most 16 output columns take the narrow kernel."""
+    m, k = 150, 70
+    A = orc.canon(synthgen.uniform(m if opA == "N" else k, k if opA == "N" else m, C, 95))
+    B = orc.canon(synthgen.uniform(k, ncols, C, 96))
+    Cm = orc.canon(synthgen.uniform(m, ncols, C, 97))
+    ref = orc.gemm(A, B, Cm, method=4, opA=opA, alpha_sign=-1)
+    Td = to_dev(Cm)
+    mp.gemm(to_dev(A), to_dev(B), Td, opA=opA, alpha=-1, method="4m")
+    d = orc.diff(to_host(Td), ref)
+    tol = gemm_tol(A, B, Cm, opA, "N", C, k)
+    assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)
+
+
+@pytest.mark.parametrize("C", [2, 4])
+@pytest.mark.parametrize("panel", [96, 128])
+def test_getrf_wide_panel_trsm_split(mp, orc, C, panel):
+    """Panels whose triangle does not fit in LDS solve U12 in halves."""
+    _lu_parity(mp, orc, C, 300, panel, "3m", 60 + C)
