@@ -20,8 +20,10 @@
  *
  * CONVENTIONS SHARED BY ALL ENTRY POINTS
  *  - Pointers named d_* and every mplu_zmat_t.planes are DEVICE pointers (hipMalloc'd or
- *    from a caching allocator).  The caller owns all memory; the library never allocates,
- *    frees or synchronises.  Work is enqueued on `stream` (a hipStream_t; NULL = default).
+ *    from a caching allocator).  The caller owns all memory; the library never allocates
+ *    device memory, frees or synchronises the host.  Work is enqueued on `stream` (a
+ *    hipStream_t; NULL = default); mplu_zgetrf also forks part of it onto an internal
+ *    stream and joins it back (see there).
  *  - Return value (synchronous, decided before anything is enqueued): 0 on success,
  *    -i when argument i (1-based) is invalid, or one of the MPLU_E_* codes below.
  *  - Numerical failure is reported asynchronously through d_info (LAPACK getf2 rules).
@@ -63,8 +65,12 @@ typedef struct {
   int32_t gemm;       /* mplu_gemm_t for the trailing update [MPLU_GEMM_3M]                 */
   int32_t n_slices;   /* split methods: slices per operand, 0 = automatic                   */
   int32_t slice_bits; /* split methods: bits per slice, 0 = automatic                       */
-  int32_t flags;      /* reserved, must be 0                                                */
+  int32_t flags;      /* MPLU_FLAG_* bits [0]                                               */
 } mplu_opts_t;
+
+/* mplu_zgetrf / mplu_zgesv flag: run every step on `stream` in order, without the
+ * look-ahead described under mplu_zgetrf.  The results are bitwise the same. */
+#define MPLU_FLAG_NO_LOOKAHEAD 1
 
 /* Error codes (besides -i for argument i). */
 #define MPLU_OK 0
@@ -100,6 +106,12 @@ int mplu_zgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
 /*
  * mplu_zgetrf -- P A = L U by blocked right-looking LU with partial pivoting (Sec. 3,
  * Fig. 8; "Normal LU" when opts->panel >= min(m, n)).
+ *   Look-ahead: while panel k+1 is factored on `stream`, the step-k update of the
+ *   columns right of panel k+1 runs on a second stream of the library (one per device,
+ *   created on first use and kept until the process ends), forked from and joined back
+ *   to `stream` with events, so the call still behaves as one ordered unit of work on
+ *   `stream` (also under stream capture).  Concurrent calls on one device are serialised
+ *   on that second stream.  MPLU_FLAG_NO_LOOKAHEAD keeps everything on `stream`.
  *   A (m x n) is overwritten by L (unit diagonal not stored) and U.
  *   d_ipiv: min(m,n) int32, 1-based row interchanges in LAPACK order (row k was swapped
  *           with row d_ipiv[k]-1, for k ascending).

@@ -98,9 +98,13 @@ def _stream():
     return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _opts(panel=64, method="3m", n_slices=0, slice_bits=0) -> Opts:
+FLAG_NO_LOOKAHEAD = 1
+
+
+def _opts(panel=64, method="3m", n_slices=0, slice_bits=0, lookahead=True) -> Opts:
     m = _METHODS[method] if isinstance(method, str) else int(method)
-    return Opts(int(panel), m, int(n_slices), int(slice_bits), 0)
+    return Opts(int(panel), m, int(n_slices), int(slice_bits),
+                0 if lookahead else FLAG_NO_LOOKAHEAD)
 
 
 def _work(nbytes: int, device) -> torch.Tensor:
@@ -125,11 +129,12 @@ def convert(A: torch.Tensor, Cout: int) -> torch.Tensor:
 
 
 def getrf(A: torch.Tensor, panel: int = 64, method="3m", m: int | None = None,
-          n_slices: int = 0, slice_bits: int = 0, work: torch.Tensor | None = None):
+          n_slices: int = 0, slice_bits: int = 0, work: torch.Tensor | None = None,
+          lookahead: bool = True):
     """In-place P A = L U.  Returns (ipiv int32 device tensor, info int32 device tensor)."""
     C, n = A.shape[1], A.shape[2]
     m = A.shape[3] if m is None else m
-    o = _opts(panel, method, n_slices, slice_bits)
+    o = _opts(panel, method, n_slices, slice_bits, lookahead)
     nb = ct.c_size_t()
     _check(lib().mplu_zgetrf_wsbytes(C, m, n, ct.byref(o), ct.byref(nb)), "wsbytes")
     if work is None or work.numel() < nb.value:
@@ -157,11 +162,11 @@ def getrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, trans: str = "N
 
 
 def gesv(A: torch.Tensor, B: torch.Tensor, panel: int = 64, method="3m", n_slices: int = 0,
-         slice_bits: int = 0, work: torch.Tensor | None = None):
+         slice_bits: int = 0, work: torch.Tensor | None = None, lookahead: bool = True):
     """In place: A := factors, B := X.  Returns (ipiv, info)."""
     C, n = A.shape[1], A.shape[2]
     nrhs = B.shape[2]
-    o = _opts(panel, method, n_slices, slice_bits)
+    o = _opts(panel, method, n_slices, slice_bits, lookahead)
     nb = ct.c_size_t()
     _check(lib().mplu_zgesv_wsbytes(C, n, nrhs, ct.byref(o), ct.byref(nb)), "wsbytes")
     if work is None or work.numel() < nb.value:

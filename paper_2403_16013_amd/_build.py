@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmplu.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["k_elem.hip", "k_panel.hip", "k_trsm.hip", "k_gemm.hip", "k_split.hip", "capi.cpp"]
+SOURCES = ["k_elem.hip", "k_panel.hip", "k_trsm.hip", "k_trsv.hip", "k_gemm.hip", "k_split.hip", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MPLU_ARCH", "gfx950")

@@ -6,7 +6,9 @@
 #include <stdint.h>
 #include <string.h>
 
-#include "../../include/mplu.h"
+#include <mutex>
+
+#include "mplu.h"
 #include "common.hpp"
 
 using namespace mplu;
@@ -45,9 +47,14 @@ inline int gemm_method(const mplu_opts_t *o) { return o ? o->gemm : MPLU_GEMM_3M
     if ((x) != hipSuccess) return MPLU_E_HIP; \
   } while (0)
 
+// right-hand-side counts up to this use the one-launch substitutions (k_trsv), larger
+// ones the blocked sweep of triangular solves and products
+constexpr int64_t kSvMaxRhs = 32;
+
 int getrs_ws(int C, int64_t n, int64_t nrhs, size_t *bytes) {
   *bytes = align256(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)) +
-           align256(sizeof(double) * 2 * C * (size_t)(n > 0 ? n : 1) * (size_t)(nrhs > 0 ? nrhs : 1));
+           align256(sizeof(double) * 2 * C * (size_t)(n > 0 ? n : 1) * (size_t)(nrhs > 0 ? nrhs : 1)) +
+           align256(sizeof(int32_t) * (size_t)trsv_flag_words(n, nrhs < kSvMaxRhs ? nrhs : kSvMaxRhs));
   return 0;
 }
 
@@ -66,16 +73,84 @@ inline bool split_opts_ok(int C, int method, const mplu_opts_t *o) {
   return split_supported(C, i8, S);
 }
 
-int getrf_ws(int C, int64_t m, int64_t n, const mplu_opts_t *o, size_t *bytes) {
+// getrf workspace: two panel workspaces (consecutive panels alternate, so the step-k
+// interchanges stay readable while panel k+1 is factored), then for the split methods one
+// slice workspace for the rest of the trailing matrix and one for the next panel's columns
+struct GetrfWS {
+  size_t panel, split_rest, split_next, total;
+};
+
+GetrfWS getrf_layout(int C, int64_t m, int64_t n, const mplu_opts_t *o) {
   const int64_t mn = m < n ? m : n;
   int kb = panel_width(o);
   if (mn > 0 && kb > mn) kb = (int)mn;
   if (kb < 1) kb = 1;
-  *bytes = align256(panel_ws_bytes(C, kb));
+  GetrfWS w{};
+  w.panel = align256(panel_ws_bytes(C, kb));
   const int method = gemm_method(o);
-  if (is_split(method))
-    *bytes += split_ws_bytes(C, method == MPLU_GEMM_SPLIT_I8, m, n, kb, o ? o->n_slices : 0);
+  if (is_split(method)) {
+    const bool i8 = method == MPLU_GEMM_SPLIT_I8;
+    const int S = o ? o->n_slices : 0;
+    w.split_rest = align256(split_ws_bytes(C, i8, m, n, kb, S));
+    w.split_next = align256(split_ws_bytes(C, i8, m, kb, kb, S));
+  }
+  w.total = 2 * w.panel + w.split_rest + w.split_next;
+  return w;
+}
+
+int getrf_ws(int C, int64_t m, int64_t n, const mplu_opts_t *o, size_t *bytes) {
+  *bytes = getrf_layout(C, m, n, o).total;
   return 0;
+}
+
+// The library's second stream on the current device, with the two events that order it
+// against the caller's stream.  Created on first use and kept for the process lifetime;
+// the returned lock serialises the enqueue sequences that use them.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ev_panel = nullptr, ev_rest = nullptr, ev_chain = nullptr;
+  bool ready = false;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+
+SideStream *side_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  SideStream &sd = g_side[dev];
+  if (!sd.ready) {
+    if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&sd.ev_panel, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&sd.ev_rest, hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&sd.ev_chain, hipEventDisableTiming) != hipSuccess) return nullptr;
+    sd.ready = true;
+  }
+  return &sd;
+}
+
+// the trailing update of one step restricted to columns [c0, c1): U12 := L11^-1 A12 on
+// those columns, then A22 -= L21 U12 on them
+hipError_t step_trsm(int C, ZM a, int64_t j, int jb, int64_t c0, int64_t c1, hipStream_t s) {
+  if (c1 <= c0) return hipSuccess;
+  return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s);
+}
+
+hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
+                     int64_t c1, void *split_ws, hipStream_t s) {
+  if (c1 <= c0 || j + jb >= m) return hipSuccess;
+  if (is_split(method))
+    return launch_gemm_split(C, method == MPLU_GEMM_SPLIT_I8, S, 'N', 'N', m - j - jb, c1 - c0,
+                             jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, split_ws, s);
+  return launch_gemm(C, method == MPLU_GEMM_3M ? 1 : 0, 'N', 'N', m - j - jb, c1 - c0, jb, -1, a,
+                     j + jb, j, a, j, c0, 1, a, j + jb, c0, s);
+}
+
+hipError_t step_update(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
+                       int64_t c1, void *split_ws, hipStream_t s) {
+  hipError_t e = step_trsm(C, a, j, jb, c0, c1, s);
+  if (e != hipSuccess) return e;
+  return step_gemm(C, method, S, a, m, j, jb, c0, c1, split_ws, s);
 }
 
 }  // namespace
@@ -136,7 +211,7 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   const int64_t mn = m < n ? m : n;
   if (mn > 0 && d_ipiv == nullptr) return -5;
   if (d_info == nullptr) return -6;
-  if (opts && (opts->panel < 0 || opts->flags != 0)) return -7;
+  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -7;
   const int method = gemm_method(opts);
   if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M && method != MPLU_GEMM_SPLIT_F64 &&
       method != MPLU_GEMM_SPLIT_I8)
@@ -156,25 +231,66 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     if (panel_geometry(C, m - j, jb).G == 0) return MPLU_E_UNSUPPORTED;
   }
   HIPCHK(launch_fill_i32(d_info, 0, 1, s));
+  if (mn == 0) return 0;
   const ZM a = zm(A);
-  void *split_ws = (char *)d_work + align256(panel_ws_bytes(C, kb));
-  for (int64_t j = 0; j < mn; j += kb) {
-    const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
-    HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, d_work, s));
-    HIPCHK(launch_laswp(C, a, j, j + jb, n, d_work, jb, s));
-    if (j + jb < n) {
-      HIPCHK(launch_trsm(C, true, true, false, a, j, jb, a, j, j + jb, n - j - jb, s));
-      if (j + jb < m) {
-        if (is_split(method))
-          HIPCHK(launch_gemm_split(C, method == MPLU_GEMM_SPLIT_I8, opts ? opts->n_slices : 0,
-                                   'N', 'N', m - j - jb, n - j - jb, jb, -1, a, j + jb, j, a, j,
-                                   j + jb, 1, a, j + jb, j + jb, split_ws, s));
-        else
-          HIPCHK(launch_gemm(C, method == MPLU_GEMM_3M ? 1 : 0, 'N', 'N', m - j - jb, n - j - jb,
-                             jb, -1, a, j + jb, j, a, j, j + jb, 1, a, j + jb, j + jb, s));
-      }
+  const GetrfWS L = getrf_layout(C, m, n, opts);
+  char *wb = (char *)d_work;
+  void *pws[2] = {wb, wb + L.panel};
+  void *split_rest = wb + 2 * L.panel;
+  void *split_next = wb + 2 * L.panel + L.split_rest;
+  const int S = opts ? opts->n_slices : 0;
+
+  unsigned base[2] = {0u, 0u};
+  HIPCHK(panel_ws_clear(pws[0], s));
+  HIPCHK(panel_ws_clear(pws[1], s));
+  if (opts && (opts->flags & MPLU_FLAG_NO_LOOKAHEAD)) {
+    for (int64_t j = 0; j < mn; j += kb) {
+      const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
+      HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, pws[0], &base[0], s));
+      HIPCHK(launch_laswp(C, a, j, j + jb, n, pws[0], jb, s));
+      HIPCHK(step_update(C, method, S, a, m, j, jb, j + jb, n, split_rest, s));
     }
+    return 0;
   }
+
+  // Look-ahead by one panel.  After panel k (columns [j, j+jb)) is factored:
+  //   caller's stream:  interchanges, U12 and A22 update of the next panel's columns,
+  //                     then panel k+1;
+  //   second stream:    interchanges of the columns left of the panel and right of the
+  //                     next panel, then their U12 / A22 update.
+  // The next panel's columns are up to date through step k-1 only after the second
+  // stream's step k-1, which the caller's stream waits for first.
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStream *sd = side_stream();
+  if (!sd) return MPLU_E_HIP;
+  const hipStream_t b = sd->s;
+  HIPCHK(launch_panel(C, a, 0, m, (int)(mn < kb ? mn : kb), d_ipiv, d_info, pws[0], &base[0], s));
+  int k = 0;
+  for (int64_t j = 0; j < mn; j += kb, ++k) {
+    const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
+    void *pw = pws[k & 1];
+    const int64_t nx0 = j + jb;  // next panel's columns [nx0, nx1)
+    const int64_t nx1 = nx0 < mn ? nx0 + ((mn - nx0) < kb ? (mn - nx0) : kb) : nx0;
+    HIPCHK(hipEventRecord(sd->ev_panel, s));
+    if (k > 0) HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));
+    HIPCHK(hipStreamWaitEvent(b, sd->ev_panel, 0));
+    HIPCHK(launch_laswp(C, a, j, nx1, n, pw, jb, b));
+    if (nx1 > nx0) {
+      HIPCHK(launch_laswp(C, a, 0, nx0, nx1, pw, jb, s));
+      HIPCHK(step_update(C, method, S, a, m, j, jb, nx0, nx1, split_next, s));
+    }
+    // the second stream's product waits until the next panel is about to start, so the
+    // panel's workgroups are dispatched before the product fills the device
+    HIPCHK(hipEventRecord(sd->ev_chain, s));
+    HIPCHK(step_trsm(C, a, j, jb, nx1, n, b));
+    HIPCHK(hipStreamWaitEvent(b, sd->ev_chain, 0));
+    HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx1, n, split_rest, b));
+    HIPCHK(hipEventRecord(sd->ev_rest, b));
+    if (nx1 > nx0)
+      HIPCHK(launch_panel(C, a, nx0, m, (int)(nx1 - nx0), d_ipiv, d_info, pws[(k + 1) & 1],
+                          &base[(k + 1) & 1], s));
+  }
+  HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));
   return 0;
 }
 
@@ -209,6 +325,21 @@ int mplu_zgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_zmat_t LU,
   const ZM w{wbuf, n, n * nrhs};
   const ZM lu = zm(LU), b = zm(B);
   HIPCHK(launch_perm(d_ipiv, n, perm, s));
+  if (nrhs <= kSvMaxRhs) {
+    int32_t *flags = (int32_t *)((char *)wbuf + align256(sizeof(double) * 2 * C * (size_t)n * (size_t)nrhs));
+    if (trans == 'N') {
+      HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, false, s));            // P b
+      HIPCHK(launch_trsv(C, true, true, false, lu, w, n, nrhs, flags, s));      // L y = P b
+      HIPCHK(launch_trsv(C, false, false, false, lu, w, n, nrhs, flags, s));    // U x = y
+      HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, true, s));
+    } else {
+      HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, false, s));
+      HIPCHK(launch_trsv(C, false, false, true, lu, w, n, nrhs, flags, s));     // U^H z = b
+      HIPCHK(launch_trsv(C, true, true, true, lu, w, n, nrhs, flags, s));       // L^H w = z
+      HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, true, s));              // x = P^T w
+    }
+    return 0;
+  }
   const int NB = kSolveBlock;
   const int64_t nblk = (n + NB - 1) / NB;
   if (trans == 'N') {

@@ -58,10 +58,14 @@ struct PanelGeom {
 PanelGeom panel_geometry(int C, int64_t mp, int kb);
 size_t panel_ws_bytes(int C, int kb);
 
+// clear the barrier words of a panel workspace (once per factorisation, before its
+// first panel)
+hipError_t panel_ws_clear(void *ws, hipStream_t s);
 // factor rows [j, m) x columns [j, j+kb) in place; writes ipiv[j..j+kb), info, and the
-// swap list for the other columns into the workspace
+// swap list for the other columns into the workspace.  *base: barrier arrivals already
+// counted on this workspace since it was cleared; advanced past this panel's.
 hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
-                        int32_t *info, void *ws, hipStream_t s);
+                        int32_t *info, void *ws, unsigned *base, hipStream_t s);
 // apply the swap list left by launch_panel to columns [0, c0) and [c1, n)
 hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
                         int kb, hipStream_t s);
@@ -85,6 +89,12 @@ hipError_t launch_gemm_split(int C, bool i8, int S, char opA, char opB, int64_t 
                              int64_t k, int alpha, ZM A, int64_t ai, int64_t aj, ZM B,
                              int64_t bi, int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj,
                              void *ws, hipStream_t s);
+
+// op(T) X = X for the whole n x n triangle of Tm and nrhs columns of Xm in one launch;
+// flags: trsv_flag_words(n, nrhs) int32 of workspace (cleared by the launcher)
+int64_t trsv_flag_words(int64_t n, int64_t nrhs);
+hipError_t launch_trsv(int C, bool lower, bool unit, bool conj, ZM Tm, ZM Xm, int64_t n,
+                       int64_t nrhs, int32_t *flags, hipStream_t s);
 
 // getrs helpers: perm from ipiv (n entries), then gather / scatter rows of B
 hipError_t launch_perm(const int32_t *ipiv, int64_t n, int32_t *perm, hipStream_t s);

@@ -337,10 +337,21 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
     }
     return hipErrorInvalidValue;
   }
+  // products too small to give each CU a few 32 x 32 tiles (the next panel's columns in
+  // the look-ahead, the last trailing updates) take 16 x 16 tiles, one element per
+  // thread; every element still accumulates over k in the same order, so the result does
+  // not depend on the tiling
+  const bool small = ((m + 31) / 32) * ((n + 31) / 32) < 512;
   switch (C) {
-    case 2: return m3 ? go_dd<true>(gemm_cfg(), a, s) : go_dd<false>(gemm_cfg(), a, s);
-    case 3: return m3 ? go<3, true, 32, 32, 8, 2, 2, 1>(a, s) : go<3, false, 32, 32, 8, 2, 2, 1>(a, s);
-    case 4: return m3 ? go<4, true, 32, 32, 8, 2, 2, 1>(a, s) : go<4, false, 32, 32, 8, 2, 2, 1>(a, s);
+    case 2:
+      if (small) return m3 ? go<2, true, 16, 16, 16, 1, 1, 1>(a, s) : go<2, false, 16, 16, 16, 1, 1, 1>(a, s);
+      return m3 ? go_dd<true>(gemm_cfg(), a, s) : go_dd<false>(gemm_cfg(), a, s);
+    case 3:
+      if (small) return m3 ? go<3, true, 16, 16, 16, 1, 1, 1>(a, s) : go<3, false, 16, 16, 16, 1, 1, 1>(a, s);
+      return m3 ? go<3, true, 32, 32, 8, 2, 2, 1>(a, s) : go<3, false, 32, 32, 8, 2, 2, 1>(a, s);
+    case 4:
+      if (small) return m3 ? go<4, true, 16, 16, 16, 1, 1, 1>(a, s) : go<4, false, 16, 16, 16, 1, 1, 1>(a, s);
+      return m3 ? go<4, true, 32, 32, 8, 2, 2, 1>(a, s) : go<4, false, 32, 32, 8, 2, 2, 1>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -11,6 +11,8 @@
 // scales its part of the column by the pivot's reciprocal and applies the rank-1 update
 // to its rows.  Nothing else touches global memory until the panel is written back.
 #include <limits.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include "common.hpp"
 
@@ -69,25 +71,38 @@ static inline size_t panel_lds(int C, int kb, int R) {
   return align256(b);
 }
 
+// compute units of the current device (the panel's workgroups must all be resident)
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cus[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cus[dev] = v;
+  }
+  return cus[dev];
+}
+
 PanelGeom panel_geometry(int C, int64_t mp, int kb) {
   PanelGeom g{0, 0, 0};
   if (mp <= 0 || kb <= 0 || kb > PKBMAX) return g;
   // largest row count per workgroup that fits in LDS (and one row per thread)
   int rmax = PNT;
   while (rmax > 1 && panel_lds(C, kb, rmax) > PLDS_BUDGET) --rmax;
-  // aim for about 64 workgroups: fewer makes the per-column barrier cheaper, more
+  // aim for about 96 workgroups: fewer makes the per-column barrier cheaper, more
   // spreads the rank-1 work; never below 8 rows each
   static int target = 0;
   if (target == 0) {
     const char *e = getenv("MPLU_PANEL_WGS");
-    target = e ? atoi(e) : 64;
-    if (target < 1) target = 64;
+    target = e ? atoi(e) : 96;
+    if (target < 1) target = 96;
   }
   int64_t R = (mp + target - 1) / target;
   if (R < 8) R = 8;
   if (R > rmax) R = rmax;
   int64_t G = (mp + R - 1) / R;
-  if (G > PGMAX) return g;
+  if (G > PGMAX || G > device_cus()) return g;
   g.G = (int)G;
   g.R = (int)R;
   g.lds = panel_lds(C, kb, (int)R);
@@ -100,6 +115,7 @@ struct PanelArgs {
   int kb, R, G;
   int32_t *ipiv, *info;
   PanelWS w;
+  unsigned base;  // arrival count left by earlier panels on this workspace
 };
 
 // lexicographic comparison of renormalised components: a strict total order that
@@ -116,9 +132,11 @@ __device__ __forceinline__ bool better(const double (&a)[C], int ia, const doubl
   return c > 0 || (c == 0 && ia < ib);
 }
 
-// argmax over the workgroup; every thread returns with the winner
+// argmax over one wave by a butterfly of exchanges; "better" is a strict total order
+// on (value, row) pairs, so every lane of every wave that reduces the same candidates
+// returns with the same winner
 template <int C>
-__device__ __forceinline__ void block_argmax(double (&v)[C], int &idx, double *sv, int *si) {
+__device__ __forceinline__ void wave_argmax(double (&v)[C], int &idx) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     double ov[C];
@@ -131,26 +149,6 @@ __device__ __forceinline__ void block_argmax(double (&v)[C], int &idx, double *s
       idx = oi;
     }
   }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) sv[w * C + c] = v[c];
-    si[w] = idx;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int ww = 0; ww < PNT / 64; ++ww) {
-    double ov[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) ov[c] = sv[ww * C + c];
-    const int oi = si[ww];
-    if (better<C>(ov, oi, v, idx)) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) v[c] = ov[c];
-      idx = oi;
-    }
-  }
-  __syncthreads();
 }
 
 // Cross-workgroup exchange.  Everything one workgroup publishes for the others goes
@@ -165,26 +163,23 @@ __device__ __forceinline__ double get(const double *p) {
   return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Split grid barrier over G co-resident workgroups: a monotonic arrival counter and a
-// generation word written by the last arrival.  The wait is bounded and its expiry is
-// sticky (every later wait returns at once), so no wave can wait forever.
-__device__ __forceinline__ void grid_arrive(unsigned *bar, unsigned G, unsigned gen) {
+// Split grid barrier over G co-resident workgroups: one arrival counter that only grows
+// (within a factorisation, consecutive panels sharing a workspace continue from the
+// count the previous one left, so it is cleared once per factorisation), polled by the
+// waiters.  The wait is bounded and its expiry is sticky (every later wait returns at
+// once), so no wave can wait forever.
+__device__ __forceinline__ void grid_arrive(unsigned *bar) {
   __builtin_amdgcn_s_waitcnt(0);  // this wave's published stores have completed
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned target = gen + 1;
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-    if (arrived == G * target)
-      __hip_atomic_store(&bar[1], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  // the waiters watch the counter itself, so the old value is not needed
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void grid_wait(unsigned *bar, unsigned gen) {
+__device__ __forceinline__ void grid_wait(unsigned *bar, unsigned want) {
   if (threadIdx.x == 0) {
-    const unsigned target = gen + 1;
     unsigned spins = 0;
-    while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - want >
+           0x7fffffffu) {  // counter < want (modular)
       if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > SPIN_LIMIT) {
@@ -207,9 +202,12 @@ __device__ __forceinline__ void grid_wait(unsigned *bar, unsigned gen) {
 template <int C>
 __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   extern __shared__ double smem[];
+  // the panel is a chain of short dependent steps; when it shares CUs with the trailing
+  // update its waves should win instruction issue
+  __builtin_amdgcn_s_setprio(3);
   constexpr int Q = 2 * C;
   const int kb = a.kb, R = a.R, G = a.G;
-  const int g = blockIdx.x, t = threadIdx.x;
+  const int g = blockIdx.x, t = threadIdx.x, lane = t & 63;
   const int64_t mp = a.m - a.j;
   const int64_t r0 = (int64_t)g * R;
   const int nr = (int)(mp - r0 < R ? (mp - r0 > 0 ? mp - r0 : 0) : R);
@@ -239,22 +237,29 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     double *cand = a.w.cand + (size_t)par * PGMAX * Q * kb;
     double *rowk = a.w.rowk + (size_t)par * Q * kb;
 
-    // (1) local pivot candidate among rows >= k (column k is up to date)
+    // (1) local pivot candidate among rows >= k (column k is up to date); every wave
+    // reduces all of this workgroup's rows, so no workgroup barrier is needed
     double v[C];
     int idx = INT_MAX;
 #pragma unroll
     for (int c = 0; c < C; ++c) v[c] = 0.0;
-    if (t < nr && r0 + t >= k) {
-      double re[C], im[C];
+    for (int r = lane; r < nr; r += 64) {
+      if (r0 + r >= k) {
+        double re[C], im[C], cv[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        re[c] = SA(k, c, t);
-        im[c] = SA(k, C + c, t);
+        for (int c = 0; c < C; ++c) {
+          re[c] = SA(k, c, r);
+          im[c] = SA(k, C + c, r);
+        }
+        mp::cabs1<C>(re, im, cv);
+        if (better<C>(cv, (int)(r0 + r), v, idx)) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) v[c] = cv[c];
+          idx = (int)(r0 + r);
+        }
       }
-      mp::cabs1<C>(re, im, v);
-      idx = (int)(r0 + t);
     }
-    block_argmax<C>(v, idx, sRedV, sRedI);
+    wave_argmax<C>(v, idx);
 
     // (2) publish the candidate (value, row, row contents) and, if owned, row k
     if (t == 0) {
@@ -276,7 +281,7 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
         put(&rowk[q * kb + c], SA(c, q, lr));
       }
     }
-    grid_arrive(a.w.bar, (unsigned)G, (unsigned)k);
+    grid_arrive(a.w.bar);
 
     // (3) while the barrier is in flight: the pending step k-1 update of columns > k
     if (!prev_zero && k + 1 < kb) {
@@ -304,22 +309,25 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
         }
       }
     }
-    grid_wait(a.w.bar, (unsigned)k);
+    grid_wait(a.w.bar, a.base + (unsigned)G * (unsigned)(k + 1));
 
-    // (4) global winner
+    // (4) global winner: every wave loads all G candidates (one round trip) and reduces
     double bv[C];
     int bi = INT_MAX;
 #pragma unroll
     for (int c = 0; c < C; ++c) bv[c] = 0.0;
-    if (t < G) {
-      const double ix = get(&part[t * (C + 1) + C]);
-      if (ix >= 0.0) {
+    for (int gg = lane; gg < G; gg += 64) {
+      double cv[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) bv[c] = get(&part[t * (C + 1) + c]);
+      for (int c = 0; c < C; ++c) cv[c] = get(&part[gg * (C + 1) + c]);
+      const double ix = get(&part[gg * (C + 1) + C]);
+      if (ix >= 0.0 && better<C>(cv, (int)ix, bv, bi)) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) bv[c] = cv[c];
         bi = (int)ix;
       }
     }
-    block_argmax<C>(bv, bi, sRedV, sRedI);
+    wave_argmax<C>(bv, bi);
     const int p = bi;
     const int gp = p / R;
     for (int e = t; e < Q * kb; e += PNT) {
@@ -503,26 +511,31 @@ __global__ __launch_bounds__(256) void k_laswp(ZM A, int64_t c0, int64_t c1, int
   if (w >= ncols || cnt == 0) return;
   const int64_t col = w < c0 ? w : c1 + (w - c0);
   constexpr int Q = 2 * C;
+  // every read before any write, so the loads of all planes are in flight together
+  const int nh = (cnt + 63) / 64;  // at most 4 (cnt <= 2 kb <= 256)
+  double *col0 = A.p + col * A.ld;
+  double v[4][Q];
+  int32_t sr[4], ds[4];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    double *base = A.p + (int64_t)q * A.ps + col * A.ld;
-    double v[4];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int e = lane + 64 * h;
-      v[h] = (e < cnt) ? base[src[e]] : 0.0;
-    }
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int e = lane + 64 * h;
-      if (e < cnt) base[dst[e]] = v[h];
-    }
+  for (int h = 0; h < 4; ++h) {
+    const int e = lane + 64 * h;
+    sr[h] = (h < nh && e < cnt) ? src[e] : -1;
+    ds[h] = (h < nh && e < cnt) ? dst[e] : -1;
   }
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[h][q] = (sr[h] >= 0) ? col0[(int64_t)q * A.ps + sr[h]] : 0.0;
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (ds[h] >= 0) col0[(int64_t)q * A.ps + ds[h]] = v[h][q];
 }
 
 template <int C>
 static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
-                                 int32_t *info, void *ws, hipStream_t s) {
+                                 int32_t *info, void *ws, unsigned *base, hipStream_t s) {
   const PanelGeom geo = panel_geometry(C, m - j, kb);
   if (geo.G == 0) return hipErrorInvalidValue;
   PanelArgs a;
@@ -535,6 +548,8 @@ static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ip
   a.ipiv = ipiv;
   a.info = info;
   a.w = carve(ws, C, kb, nullptr);
+  a.base = *base;
+  *base += (unsigned)geo.G * (unsigned)kb;
   static bool attr_done[5] = {false, false, false, false, false};
   if (!attr_done[C]) {
     hipError_t e = hipFuncSetAttribute((const void *)k_panel<C>,
@@ -543,19 +558,23 @@ static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ip
     if (e != hipSuccess) return e;
     attr_done[C] = true;
   }
-  hipError_t e = launch_fill_i32((int32_t *)a.w.bar, 0, 4, s);
-  if (e != hipSuccess) return e;
-  void *args[] = {&a};
-  return hipLaunchCooperativeKernel((const void *)k_panel<C>, dim3(geo.G), dim3(PNT), args,
-                                    (unsigned)geo.lds, s);
+  // G never exceeds the CU count and one workgroup fits a CU, so every workgroup becomes
+  // resident once the kernels sharing the device retire theirs: an ordinary launch
+  // suffices, and it may run beside the trailing update on another stream
+  hipLaunchKernelGGL((k_panel<C>), dim3(geo.G), dim3(PNT), geo.lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t panel_ws_clear(void *ws, hipStream_t s) {
+  return launch_fill_i32((int32_t *)ws, 0, 4, s);
 }
 
 hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
-                        int32_t *info, void *ws, hipStream_t s) {
+                        int32_t *info, void *ws, unsigned *base, hipStream_t s) {
   switch (C) {
-    case 2: return launch_panel_t<2>(A, j, m, kb, ipiv, info, ws, s);
-    case 3: return launch_panel_t<3>(A, j, m, kb, ipiv, info, ws, s);
-    case 4: return launch_panel_t<4>(A, j, m, kb, ipiv, info, ws, s);
+    case 2: return launch_panel_t<2>(A, j, m, kb, ipiv, info, ws, base, s);
+    case 3: return launch_panel_t<3>(A, j, m, kb, ipiv, info, ws, base, s);
+    case 4: return launch_panel_t<4>(A, j, m, kb, ipiv, info, ws, base, s);
   }
   return hipErrorInvalidValue;
 }

@@ -1,11 +1,10 @@
-// k_trsm.hip -- solve op(T) X = X for one nb x nb triangular block T (nb <= 128),
-// in place, many right-hand-side columns at once.
+// k_trsm.hip -- solve op(T) X = X for one nb x nb triangular block T, in place, many
+// right-hand-side columns at once.
 //
 // Used for the block row of U in the blocked LU (U12 := L11^-1 A12, Kouya Sec. 3) and for
-// the diagonal blocks of the forward / backward substitutions (Sec. 4).  Each workgroup
-// owns a strip of columns of X held in LDS, stages the triangle in LDS and sweeps the nb
-// rows in order.  Blocks whose triangle does not fit are split in halves around a 4M
-// product.  Element operations use the 4M complex product with one rounding per part
+// the diagonal blocks of the blocked substitutions (Sec. 4).  Each workgroup stages the
+// triangle in LDS and sweeps a strip of columns of X, one column per wave and one row
+// per lane.  Blocks of more than 64 rows are split in halves around a 4M product.  Element operations use the 4M complex product with one rounding per part
 // (Eq. 4m).
 #include "common.hpp"
 
@@ -35,30 +34,35 @@ __device__ __forceinline__ void ld_opT(const TrsmArgs &a, int r, int i, double (
   }
 }
 
-// LOWER: op(T) is lower triangular (forward sweep); UNIT: unit diagonal.
+// value of lane s (s uniform across the wave)
+__device__ __forceinline__ double wbcast(double v, int s) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), s);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), s);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// LOWER: op(T) is lower triangular (forward sweep); UNIT: unit diagonal.  nb <= 64.
 // The strict triangle of op(T) is staged once in LDS, packed by columns in component
-// planes (column i holds rows i+1..nb-1 when LOWER, rows 0..i-1 otherwise), so the sweep
-// reads it at LDS latency; the diagonal is kept as reciprocals.
+// planes (column i holds rows i+1..nb-1 when LOWER, rows 0..i-1 otherwise), with the
+// reciprocals of the diagonal.  Each wave then owns TW right-hand-side columns at a
+// time, one row per lane: a step finishes unknown s on lane s, broadcasts it across the
+// wave and updates the other rows, with no workgroup barrier inside the sweep.
 template <int C, bool LOWER, bool UNIT, bool CONJ>
 __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   extern __shared__ double smem[];
   constexpr int Q = 2 * C;
-  const int nb = a.nb, NBC = a.nbc, t = threadIdx.x;
+  constexpr int TW = 2;  // columns per wave in flight
+  const int nb = a.nb, NBC = a.nbc, t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int ntri = nb * (nb - 1) / 2;
   const int64_t cb = a.c0 + (int64_t)blockIdx.x * NBC;
   const int64_t left = a.c0 + a.ncols - cb;
   const int ncl = (int)(left < NBC ? left : NBC);
-  double *sX = smem;                          // [nb][Q][NBC]
-  double *sR = sX + (size_t)nb * Q * NBC;     // [nb][Q] reciprocals of the diagonal
-  double *sT = sR + (size_t)nb * Q;           // [Q][ntri] packed strict triangle
+  double *sR = smem;                    // [Q][nb] reciprocals of the diagonal
+  double *sT = sR + (size_t)nb * Q;     // [Q][ntri] packed strict triangle
 
   auto col_off = [&](int i) { return LOWER ? i * (nb - 1) - i * (i - 1) / 2 : i * (i - 1) / 2; };
 
-  for (int e = t; e < nb * ncl * Q; e += 256) {
-    const int r = e % nb, rest = e / nb, cc = rest % ncl, q = rest / ncl;
-    sX[((size_t)r * Q + q) * NBC + cc] = a.X.p[(int64_t)q * a.X.ps + (cb + cc) * a.X.ld + a.x0 + r];
-  }
-  // strict triangle: enumerate (column i, row r) pairs column by column
   for (int e = t; e < ntri; e += 256) {
     int i, r;
     if (LOWER) {  // column i has nb-1-i entries
@@ -87,70 +91,74 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
       mp::zrecip<C>(dr, di, rr, ri);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        sR[i * Q + c] = rr[c];
-        sR[i * Q + C + c] = ri[c];
+        sR[c * nb + i] = rr[c];
+        sR[(C + c) * nb + i] = ri[c];
       }
     }
   }
   __syncthreads();
 
-  for (int s = 0; s < nb; ++s) {
-    const int i = LOWER ? s : nb - 1 - s;
-    if (!UNIT) {
-      for (int cc = t; cc < ncl; cc += 256) {
-        double xr[C], xi[C], rr[C], ri[C], orr[C], oi[C];
+  double rr[C], ri[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          xr[c] = sX[((size_t)i * Q + c) * NBC + cc];
-          xi[c] = sX[((size_t)i * Q + C + c) * NBC + cc];
-          rr[c] = sR[i * Q + c];
-          ri[c] = sR[i * Q + C + c];
-        }
-        mp::zmul<C>(xr, xi, rr, ri, orr, oi);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          sX[((size_t)i * Q + c) * NBC + cc] = orr[c];
-          sX[((size_t)i * Q + C + c) * NBC + cc] = oi[c];
-        }
-      }
-      __syncthreads();
-    }
-    const int rlo = LOWER ? i + 1 : 0;
-    const int rcnt = LOWER ? nb - i - 1 : i;
-    const int off = col_off(i);
-    for (int e = t; e < rcnt * ncl; e += 256) {
-      const int r = rlo + e / ncl, cc = e % ncl;
-      double tr[C], ti[C], xr[C], xi[C], yr[C], yi[C];
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        tr[c] = sT[(size_t)c * ntri + off + (r - rlo)];
-        ti[c] = sT[(size_t)(C + c) * ntri + off + (r - rlo)];
-        xr[c] = sX[((size_t)r * Q + c) * NBC + cc];
-        xi[c] = sX[((size_t)r * Q + C + c) * NBC + cc];
-        yr[c] = sX[((size_t)i * Q + c) * NBC + cc];
-        yi[c] = sX[((size_t)i * Q + C + c) * NBC + cc];
-      }
-      mp::zfms<C>(xr, xi, tr, ti, yr, yi, xr, xi);
-#pragma unroll
-      for (int c = 0; c < C; ++c) {
-        sX[((size_t)r * Q + c) * NBC + cc] = xr[c];
-        sX[((size_t)r * Q + C + c) * NBC + cc] = xi[c];
-      }
-    }
-    __syncthreads();
+  for (int c = 0; c < C; ++c) {
+    rr[c] = (!UNIT && lane < nb) ? sR[c * nb + lane] : 0.0;
+    ri[c] = (!UNIT && lane < nb) ? sR[(C + c) * nb + lane] : 0.0;
   }
 
-  for (int e = t; e < nb * ncl * Q; e += 256) {
-    const int r = e % nb, rest = e / nb, cc = rest % ncl, q = rest / ncl;
-    a.X.p[(int64_t)q * a.X.ps + (cb + cc) * a.X.ld + a.x0 + r] = sX[((size_t)r * Q + q) * NBC + cc];
+  for (int cc0 = w * TW; cc0 < ncl; cc0 += 4 * TW) {
+    double xr[TW][C], xi[TW][C];
+#pragma unroll
+    for (int h = 0; h < TW; ++h) {
+      if (lane < nb && cc0 + h < ncl) {
+        ld_z<C>(a.X, a.x0 + lane, cb + cc0 + h, xr[h], xi[h]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) xr[h][c] = xi[h][c] = 0.0;
+      }
+    }
+    for (int u = 0; u < nb; ++u) {
+      const int i = LOWER ? u : nb - 1 - u;
+      if (!UNIT && lane == i) {
+#pragma unroll
+        for (int h = 0; h < TW; ++h) {
+          double orr[C], oi[C];
+          mp::zmul<C>(xr[h], xi[h], rr, ri, orr, oi);
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            xr[h][c] = orr[c];
+            xi[h][c] = oi[c];
+          }
+        }
+      }
+      const bool upd = LOWER ? (lane > i && lane < nb) : (lane < i);
+      const int off = col_off(i) + (LOWER ? lane - i - 1 : lane);
+      double tr[C], ti[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        tr[c] = upd ? sT[(size_t)c * ntri + off] : 0.0;
+        ti[c] = upd ? sT[(size_t)(C + c) * ntri + off] : 0.0;
+      }
+#pragma unroll
+      for (int h = 0; h < TW; ++h) {
+        double yr[C], yi[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          yr[c] = wbcast(xr[h][c], i);
+          yi[c] = wbcast(xi[h][c], i);
+        }
+        if (upd) mp::zfms<C>(xr[h], xi[h], tr, ti, yr, yi, xr[h], xi[h]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < TW; ++h)
+      if (lane < nb && cc0 + h < ncl) st_z<C>(a.X, a.x0 + lane, cb + cc0 + h, xr[h], xi[h]);
   }
 }
 
 template <int C, bool LOWER, bool UNIT, bool CONJ>
 static hipError_t go(const TrsmArgs &a, hipStream_t s) {
   constexpr int Q = 2 * C;
-  const size_t lds = sizeof(double) * ((size_t)a.nb * Q * a.nbc + (size_t)a.nb * Q +
-                                        (size_t)Q * (a.nb * (a.nb - 1) / 2));
+  const size_t lds = sizeof(double) * ((size_t)a.nb * Q + (size_t)Q * (a.nb * (a.nb - 1) / 2));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void *)k_trsm<C, LOWER, UNIT, CONJ>,
@@ -175,15 +183,11 @@ static hipError_t dispatch(bool lower, bool unit, bool conj, const TrsmArgs &a, 
   return conj ? go<C, false, false, true>(a, s) : go<C, false, false, false>(a, s);
 }
 
-static inline size_t tri_fixed(int C, int nb) {
-  return sizeof(double) * 2 * C * ((size_t)nb + (size_t)nb * (nb - 1) / 2);
-}
-
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
                        ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s) {
   if (nb <= 0 || ncols <= 0) return hipSuccess;
-  if (tri_fixed(C, nb) + sizeof(double) * 2 * C * nb > 128 * 1024) {
-    // the packed triangle does not fit: split op(T) into halves,
+  if (nb > 64) {
+    // one row per lane: split op(T) into halves,
     //   lower op:  X1 = T11^-1 X1;  X2 -= T21 X1;  X2 = T22^-1 X2
     //   upper op:  X2 = T22^-1 X2;  X1 -= T12 X2;  X1 = T11^-1 X1
     const int h = nb / 2, r = nb - h;
@@ -213,12 +217,11 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
   a.x0 = x0;
   a.c0 = c0;
   a.ncols = ncols;
-  // columns per workgroup: the packed triangle and the diagonal take their share of the
-  // LDS, the column strip the rest (at most 16 columns)
-  const size_t fixed = tri_fixed(C, nb);
-  int nbc = 16;
-  while (nbc > 1 && fixed + sizeof(double) * (size_t)nb * 2 * C * nbc > 160 * 1024) nbc >>= 1;
-  a.nbc = nbc;
+  // columns per workgroup: a multiple of the 8 the four waves take per pass, enough to
+  // spread over about 256 workgroups
+  int64_t nbc = (a.ncols + 255) / 256;
+  nbc = (nbc + 7) / 8 * 8;
+  a.nbc = (int)(nbc < 8 ? 8 : nbc);
   switch (C) {
     case 2: return dispatch<2>(lower, unit, conj, a, s);
     case 3: return dispatch<3>(lower, unit, conj, a, s);

@@ -150,8 +150,11 @@ def test_getrf_rectangular(mp, orc, shape):
 
 @pytest.mark.parametrize("C", CS)
 @pytest.mark.parametrize("trans", ["N", "C"])
-def test_getrs_vs_oracle(mp, orc, C, trans):
-    n, nrhs = 150, 3
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 6, 40])
+def test_getrs_vs_oracle(mp, orc, C, trans, nrhs):
+    """One-launch substitutions (up to 32 right-hand sides, in groups of 1, 2 or 4) and
+    the blocked sweep (more), ragged last block row (n = 2 * 64 + 22)."""
+    n = 150
     A = orc.canon(synthgen.uniform(n, n, C, 50 + C))
     B = orc.canon(synthgen.uniform(n, nrhs, C, 60 + C))
     LUo, ipo, _ = orc.getf2(A)
@@ -342,3 +345,47 @@ def test_narrow_gemm_vs_oracle(mp, orc, C, ncols, opA):
 def test_getrf_wide_panel_trsm_split(mp, orc, C, panel):
     """Panels whose triangle does not fit in LDS solve U12 in halves."""
     _lu_parity(mp, orc, C, 300, panel, "3m", 60 + C)
+
+
+# ---------------------------------------------------------------- look-ahead schedule
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["4m", "3m", "split_i8", "split_f64"])
+@pytest.mark.parametrize("shape", [(300, 300), (333, 200), (200, 333)])
+def test_lookahead_bitwise_equals_in_order(mp, orc, C, method, shape):
+    """The two-stream look-ahead schedule performs the same operations on every element
+    as the in-order one, so factors and pivots agree bit for bit (ragged last panel,
+    tall and wide shapes)."""
+    m, n = shape
+    A = orc.canon(synthgen.uniform(m, n, C, 90 + C))
+    outs = []
+    for la in (False, True):
+        T = to_dev(A)
+        ipiv, info = mp.getrf(T, panel=64, method=method, m=m, lookahead=la)
+        sync()
+        outs.append((to_host(T), ipiv.cpu().numpy(), int(info.item())))
+    assert outs[0][2] == outs[1][2] == 0
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_lookahead_repeated_calls_and_gesv(mp, orc):
+    """Back-to-back look-ahead factorisations reusing one workspace, then a solve on the
+    caller's stream, all agree with the in-order schedule."""
+    import torch
+
+    n, C = 260, 2
+    A = orc.canon(synthgen.uniform(n, n, C, 95))
+    Bm = orc.canon(synthgen.uniform(n, 3, C, 96))
+    ref = []
+    T = to_dev(A)
+    Bd = to_dev(Bm)
+    mp.gesv(T, Bd, panel=32, method="3m", lookahead=False)
+    sync()
+    ref = (to_host(T), to_host(Bd))
+    work = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        T = to_dev(A)
+        Bd = to_dev(Bm)
+        mp.gesv(T, Bd, panel=32, method="3m", work=work)
+        sync()
+        assert np.array_equal(to_host(T), ref[0]) and np.array_equal(to_host(Bd), ref[1])
