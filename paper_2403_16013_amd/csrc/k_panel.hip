@@ -29,7 +29,7 @@ static constexpr int32_t MPLU_SYNC_TIMEOUT = -9999;  // mirrors MPLU_INFO_SYNC_T
 
 // ------------------------------------------------------------------ workspace layout
 // [0, 256)              barrier words: count, generation, timeout flag
-// part  : 2 x PGMAX x (C+1) doubles  (cabs1 components, row index)
+// part  : 2 x PGMAX x (3C+1) doubles  (cabs1 components, row index, the complex pivot)
 // cand  : 2 x PGMAX x 2C x kb doubles
 // rowk  : 2 x 2C x kb doubles
 // swl   : 1 + 2 x (2 kb) int32  (count, dst rows, src rows)
@@ -47,7 +47,7 @@ static inline PanelWS carve(void *ws, int C, int kb, size_t *total) {
   PanelWS w;
   w.bar = (unsigned *)b;
   w.part = (double *)(b + off);
-  off = align256(off + sizeof(double) * 2 * PGMAX * (C + 1));
+  off = align256(off + sizeof(double) * 2 * PGMAX * (3 * C + 1));
   w.cand = (double *)(b + off);
   off = align256(off + sizeof(double) * 2 * PGMAX * 2 * C * kb);
   w.rowk = (double *)(b + off);
@@ -124,31 +124,73 @@ struct PanelArgs {
 template <int C>
 __device__ __forceinline__ bool better(const double (&a)[C], int ia, const double (&b)[C],
                                        int ib) {
-  if (ia == INT_MAX) return false;
-  if (ib == INT_MAX) return true;
   int c = 0;
 #pragma unroll
   for (int k = C - 1; k >= 0; --k) c = (a[k] > b[k]) ? 1 : ((a[k] < b[k]) ? -1 : c);
-  return c > 0 || (c == 0 && ia < ib);
+  // no branches: a missing candidate (row INT_MAX) loses to any present one
+  const bool a_ok = ia != INT_MAX, b_ok = ib != INT_MAX;
+  return a_ok & (!b_ok | (c > 0) | ((c == 0) & (ia < ib)));
 }
 
-// argmax over one wave by a butterfly of exchanges; "better" is a strict total order
-// on (value, row) pairs, so every lane of every wave that reduces the same candidates
-// returns with the same winner
+// value of lane s of the wave (s uniform across the wave)
+__device__ __forceinline__ double lane_value(double v, int s) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), s);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), s);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// a double moved across lanes by the DPP pattern CTRL (within rows of 16 lanes)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int C, int CTRL>
+__device__ __forceinline__ void dpp_step(double (&v)[C], int &idx) {
+  double ov[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) ov[c] = dpp_d<CTRL>(v[c]);
+  const int oi = __builtin_amdgcn_update_dpp(0, idx, CTRL, 0xF, 0xF, false);
+  if (better<C>(ov, oi, v, idx)) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = ov[c];
+    idx = oi;
+  }
+}
+
+// argmax over one wave (all 64 lanes active): rotations by 8, 4, 2, 1 inside each row of
+// 16 lanes leave every lane with its row's winner, then the four row winners are read
+// out and compared.  "better" is a strict total order on (value, row) pairs, so every
+// lane, and every wave reducing the same candidates, ends with the same winner.
 template <int C>
 __device__ __forceinline__ void wave_argmax(double (&v)[C], int &idx) {
+  dpp_step<C, 0x128>(v, idx);  // row_ror:8
+  dpp_step<C, 0x124>(v, idx);  // row_ror:4
+  dpp_step<C, 0x122>(v, idx);  // row_ror:2
+  dpp_step<C, 0x121>(v, idx);  // row_ror:1
+  double bv[C];
+  int bi = __builtin_amdgcn_readlane(idx, 0);
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
+  for (int c = 0; c < C; ++c) bv[c] = lane_value(v[c], 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
     double ov[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) ov[c] = __shfl_xor(v[c], off);
-    const int oi = __shfl_xor(idx, off);
-    if (better<C>(ov, oi, v, idx)) {
+    for (int c = 0; c < C; ++c) ov[c] = lane_value(v[c], 16 * r);
+    const int oi = __builtin_amdgcn_readlane(idx, 16 * r);
+    if (better<C>(ov, oi, bv, bi)) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) v[c] = ov[c];
-      idx = oi;
+      for (int c = 0; c < C; ++c) bv[c] = ov[c];
+      bi = oi;
     }
   }
+#pragma unroll
+  for (int c = 0; c < C; ++c) v[c] = bv[c];
+  idx = bi;
 }
 
 // Cross-workgroup exchange.  Everything one workgroup publishes for the others goes
@@ -180,7 +222,10 @@ __device__ __forceinline__ void grid_wait(unsigned *bar, unsigned want) {
     unsigned spins = 0;
     while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - want >
            0x7fffffffu) {  // counter < want (modular)
-      if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+      // the expiry word is looked at only now and then: each look is a round trip
+      if ((spins & 255u) == 255u &&
+          __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+        break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > SPIN_LIMIT) {
         __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -206,8 +251,9 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   // update its waves should win instruction issue
   __builtin_amdgcn_s_setprio(3);
   constexpr int Q = 2 * C;
+  constexpr int PREC = 3 * C + 1;  // candidate record: cabs1, row, complex value
   const int kb = a.kb, R = a.R, G = a.G;
-  const int g = blockIdx.x, t = threadIdx.x, lane = t & 63;
+  const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t mp = a.m - a.j;
   const int64_t r0 = (int64_t)g * R;
   const int nr = (int)(mp - r0 < R ? (mp - r0 > 0 ? mp - r0 : 0) : R);
@@ -233,7 +279,7 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   bool prev_zero = true;  // no pending update before column 0
   for (int k = 0; k < kb; ++k) {
     const int par = k & 1;
-    double *part = a.w.part + (size_t)par * PGMAX * (C + 1);
+    double *part = a.w.part + (size_t)par * PGMAX * PREC;
     double *cand = a.w.cand + (size_t)par * PGMAX * Q * kb;
     double *rowk = a.w.rowk + (size_t)par * Q * kb;
 
@@ -264,8 +310,12 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     // (2) publish the candidate (value, row, row contents) and, if owned, row k
     if (t == 0) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) put(&part[g * (C + 1) + c], v[c]);
-      put(&part[g * (C + 1) + C], (idx == INT_MAX) ? -1.0 : (double)idx);
+      for (int c = 0; c < C; ++c) put(&part[g * PREC + c], v[c]);
+      put(&part[g * PREC + C], (idx == INT_MAX) ? -1.0 : (double)idx);
+      if (idx != INT_MAX) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) put(&part[g * PREC + C + 1 + q], SA(k, q, (int)(idx - r0)));
+      }
     }
     if (idx != INT_MAX) {
       const int lr = (int)(idx - r0);
@@ -311,28 +361,94 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     }
     grid_wait(a.w.bar, a.base + (unsigned)G * (unsigned)(k + 1));
 
-    // (4) global winner: every wave loads all G candidates (one round trip) and reduces
-    double bv[C];
-    int bi = INT_MAX;
+    // (4) global winner.  Wave 0 alone loads the G candidate records (one round trip),
+    // reduces them, fetches the two rows and, while those are in flight, computes the
+    // reciprocal of the pivot, whose complex value came with the winner's record; the
+    // other waves pick the results up from LDS.
+    if (w == 0) {
+      double bv[C];
+      int bi = INT_MAX;
 #pragma unroll
-    for (int c = 0; c < C; ++c) bv[c] = 0.0;
-    for (int gg = lane; gg < G; gg += 64) {
-      double cv[C];
+      for (int c = 0; c < C; ++c) bv[c] = 0.0;
+      double pz[PGMAX / 64][Q], pc[PGMAX / 64][C], px[PGMAX / 64];
 #pragma unroll
-      for (int c = 0; c < C; ++c) cv[c] = get(&part[gg * (C + 1) + c]);
-      const double ix = get(&part[gg * (C + 1) + C]);
-      if (ix >= 0.0 && better<C>(cv, (int)ix, bv, bi)) {
+      for (int it = 0; it < PGMAX / 64; ++it) {
+        const int gg = lane + 64 * it;
+        const bool have = gg < G;
 #pragma unroll
-        for (int c = 0; c < C; ++c) bv[c] = cv[c];
-        bi = (int)ix;
+        for (int c = 0; c < C; ++c) pc[it][c] = have ? get(&part[gg * PREC + c]) : 0.0;
+        px[it] = have ? get(&part[gg * PREC + C]) : -1.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) pz[it][q] = have ? get(&part[gg * PREC + C + 1 + q]) : 0.0;
+      }
+#pragma unroll
+      for (int it = 0; it < PGMAX / 64; ++it) {
+        if (px[it] >= 0.0 && better<C>(pc[it], (int)px[it], bv, bi)) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) bv[c] = pc[it][c];
+          bi = (int)px[it];
+        }
+      }
+      wave_argmax<C>(bv, bi);
+      const int gp = bi / R;
+      {
+        // the record of workgroup gp sits in lane gp % 64, slot gp / 64 (gp is uniform)
+        const int gl = gp & 63, git = gp >> 6;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          double sel = pz[0][q];
+#pragma unroll
+          for (int it = 1; it < PGMAX / 64; ++it) sel = (git == it) ? pz[it][q] : sel;
+          const double val = lane_value(sel, gl);
+          if (lane == 0) sRcp[q] = val;  // the pivot itself for now
+        }
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sRedV[c] = bv[c];
+        sRedI[0] = bi;
       }
     }
-    wave_argmax<C>(bv, bi);
-    const int p = bi;
-    const int gp = p / R;
-    for (int e = t; e < Q * kb; e += PNT) {
-      sPiv[e] = get(&cand[(size_t)gp * Q * kb + e]);
-      sRowK[e] = get(&rowk[e]);
+    __syncthreads();
+    double bv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) bv[c] = sRedV[c];
+    const int p = sRedI[0];
+    {
+      // every thread fetches its share of the two rows while wave 1 inverts the pivot
+      const int gp = p / R;
+      constexpr int NE = (2 * 4 * PKBMAX + PNT - 1) / PNT;
+      double rowv[NE], rowk_v[NE];
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int e = t + i * PNT;
+        if (e < Q * kb) {
+          rowv[i] = get(&cand[(size_t)gp * Q * kb + e]);
+          rowk_v[i] = get(&rowk[e]);
+        }
+      }
+      if (t == 64) {
+        double pr[C], pi[C], rr[C], ri[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          pr[c] = sRcp[c];
+          pi[c] = sRcp[C + c];
+        }
+        mp::zrecip<C>(pr, pi, rr, ri);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          sRcp[c] = rr[c];
+          sRcp[C + c] = ri[c];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NE; ++i) {
+        const int e = t + i * PNT;
+        if (e < Q * kb) {
+          sPiv[e] = rowv[i];
+          sRowK[e] = rowk_v[i];
+        }
+      }
     }
     __syncthreads();
     // complete the two published rows with the pending step k-1 update
@@ -384,21 +500,6 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
       } else if (k >= r0 && k < r0 + nr) {
         const int lr = (int)(k - r0);
         for (int e = t; e < Q * kb; e += PNT) SA(e % kb, e / kb, lr) = sPiv[e];
-      }
-      // (6) reciprocal of the pivot
-      if (t == 0) {
-        double pr[C], pi[C], rr[C], ri[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          pr[c] = sPiv[c * kb + k];
-          pi[c] = sPiv[(C + c) * kb + k];
-        }
-        mp::zrecip<C>(pr, pi, rr, ri);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          sRcp[c] = rr[c];
-          sRcp[C + c] = ri[c];
-        }
       }
       __syncthreads();
       // (7) multipliers of column k, then column k+1 brought up to step k

@@ -137,7 +137,8 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
       unsigned spins = 0;
       while (__hip_atomic_load(const_cast<int32_t *>(f), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if (__hip_atomic_load(expiry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if ((spins & 255u) == 255u &&
+            __hip_atomic_load(expiry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
           s_expired = 1;
           break;
         }
