@@ -131,9 +131,10 @@ SideStream *side_stream() {
 
 // the trailing update of one step restricted to columns [c0, c1): U12 := L11^-1 A12 on
 // those columns, then A22 -= L21 U12 on them
-hipError_t step_trsm(int C, ZM a, int64_t j, int jb, int64_t c0, int64_t c1, hipStream_t s) {
+hipError_t step_trsm(int C, ZM a, int64_t j, int jb, int64_t c0, int64_t c1, hipStream_t s,
+                     const int32_t *swl = nullptr) {
   if (c1 <= c0) return hipSuccess;
-  return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s);
+  return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s, swl, 2 * jb);
 }
 
 hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
@@ -276,8 +277,9 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     HIPCHK(hipStreamWaitEvent(b, sd->ev_panel, 0));
     HIPCHK(launch_laswp(C, a, j, nx1, n, pw, jb, b));
     if (nx1 > nx0) {
-      HIPCHK(launch_laswp(C, a, 0, nx0, nx1, pw, jb, s));
-      HIPCHK(step_update(C, method, S, a, m, j, jb, nx0, nx1, split_next, s));
+      // the next panel's columns: interchanges and U12 in one launch, then the product
+      HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb)));
+      HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx0, nx1, split_next, s));
     }
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device

@@ -70,10 +70,19 @@ hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv
 hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
                         int kb, hipStream_t s);
 
+// the interchange list a panel leaves in its workspace (see launch_panel), and the
+// interchanges applied to columns [c0, c0+ncols) of A
+const int32_t *panel_swap_list(const void *ws, int C, int kb);
+hipError_t launch_laswp_list(int C, ZM A, int64_t c0, int64_t ncols, const int32_t *swl,
+                             int swstride, hipStream_t s);
+
 // op(T) X = X for an nb x nb triangle T of matrix Tm at (t0, t0), X = rows [x0, x0+nb) x
-// cols [c0, c0+ncols) of Xm.  lower: T stored lower; unit: unit diagonal; conj: op = ^H
+// cols [c0, c0+ncols) of Xm.  lower: T stored lower; unit: unit diagonal; conj: op = ^H.
+// swl (optional): interchange list (as left by a panel of width swstride / 2) applied to
+// those columns of Xm first.
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
-                       ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s);
+                       ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s,
+                       const int32_t *swl = nullptr, int swstride = 0);
 
 // Cm := beta Cm + alpha op(A) op(B);  method 0 = 4M, 1 = 3M
 hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,

@@ -680,6 +680,24 @@ hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv
   return hipErrorInvalidValue;
 }
 
+const int32_t *panel_swap_list(const void *ws, int C, int kb) {
+  return carve(const_cast<void *>(ws), C, kb, nullptr).swl;
+}
+
+hipError_t launch_laswp_list(int C, ZM A, int64_t c0, int64_t ncols, const int32_t *swl,
+                             int swstride, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  const int64_t blocks = (ncols + 3) / 4;
+  const int kb = swstride / 2;
+  switch (C) {
+    case 2: hipLaunchKernelGGL(k_laswp<2>, dim3((unsigned)blocks), dim3(256), 0, s, A, (int64_t)0, c0, c0 + ncols, swl, kb); break;
+    case 3: hipLaunchKernelGGL(k_laswp<3>, dim3((unsigned)blocks), dim3(256), 0, s, A, (int64_t)0, c0, c0 + ncols, swl, kb); break;
+    case 4: hipLaunchKernelGGL(k_laswp<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, (int64_t)0, c0, c0 + ncols, swl, kb); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
                         int kb, hipStream_t s) {
   const int64_t ncols = c0 + (n - c1);

@@ -19,6 +19,10 @@ struct TrsmArgs {
   ZM X;
   int64_t x0, c0, ncols;
   int nbc;  // columns per workgroup
+  // optional row interchanges to apply to this workgroup's columns first: swl[0] pairs,
+  // destination rows at swl + 1, source rows at swl + 1 + swstride (absolute rows of X)
+  const int32_t *swl;
+  int swstride;
 };
 
 // op(T)[r][i]
@@ -48,11 +52,11 @@ __device__ __forceinline__ double wbcast(double v, int s) {
 // reciprocals of the diagonal.  Each wave then owns TW right-hand-side columns at a
 // time, one row per lane: a step finishes unknown s on lane s, broadcasts it across the
 // wave and updates the other rows, with no workgroup barrier inside the sweep.
-template <int C, bool LOWER, bool UNIT, bool CONJ>
+template <int C, bool LOWER, bool UNIT, bool CONJ, int TW>
 __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   extern __shared__ double smem[];
   constexpr int Q = 2 * C;
-  constexpr int TW = 2;  // columns per wave in flight
+  // TW: columns per wave in flight (more hides latency, fewer spreads a narrow strip)
   const int nb = a.nb, NBC = a.nbc, t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int ntri = nb * (nb - 1) / 2;
   const int64_t cb = a.c0 + (int64_t)blockIdx.x * NBC;
@@ -62,6 +66,34 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   double *sT = sR + (size_t)nb * Q;     // [Q][ntri] packed strict triangle
 
   auto col_off = [&](int i) { return LOWER ? i * (nb - 1) - i * (i - 1) / 2 : i * (i - 1) / 2; };
+
+  if (a.swl) {
+    // row interchanges of this workgroup's columns, one column per wave at a time: every
+    // read of a column before any write to it (at most 256 pairs)
+    const int cnt = a.swl[0];
+    const int32_t *dst = a.swl + 1, *src = a.swl + 1 + a.swstride;
+    int32_t sr[4], ds[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int e = lane + 64 * h;
+      sr[h] = e < cnt ? src[e] : -1;
+      ds[h] = e < cnt ? dst[e] : -1;
+    }
+    for (int cc = w; cc < ncl; cc += 4) {
+      double *col0 = a.X.p + (cb + cc) * a.X.ld;
+      double v[4][Q];
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[h][q] = sr[h] >= 0 ? col0[(int64_t)q * a.X.ps + sr[h]] : 0.0;
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          if (ds[h] >= 0) col0[(int64_t)q * a.X.ps + ds[h]] = v[h][q];
+    }
+    __syncthreads();
+  }
 
   for (int e = t; e < ntri; e += 256) {
     int i, r;
@@ -155,20 +187,27 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   }
 }
 
-template <int C, bool LOWER, bool UNIT, bool CONJ>
-static hipError_t go(const TrsmArgs &a, hipStream_t s) {
+template <int C, bool LOWER, bool UNIT, bool CONJ, int TW>
+static hipError_t go_tw(const TrsmArgs &a, hipStream_t s) {
   constexpr int Q = 2 * C;
   const size_t lds = sizeof(double) * ((size_t)a.nb * Q + (size_t)Q * (a.nb * (a.nb - 1) / 2));
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_trsm<C, LOWER, UNIT, CONJ>,
+    hipError_t e = hipFuncSetAttribute((const void *)k_trsm<C, LOWER, UNIT, CONJ, TW>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
   const int64_t blocks = (a.ncols + a.nbc - 1) / a.nbc;
-  hipLaunchKernelGGL((k_trsm<C, LOWER, UNIT, CONJ>), dim3((unsigned)blocks), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_trsm<C, LOWER, UNIT, CONJ, TW>), dim3((unsigned)blocks), dim3(256), lds,
+                     s, a);
   return hipGetLastError();
+}
+
+// a strip of 4 columns per workgroup runs one column per wave
+template <int C, bool LOWER, bool UNIT, bool CONJ>
+static hipError_t go(const TrsmArgs &a, hipStream_t s) {
+  return a.nbc == 4 ? go_tw<C, LOWER, UNIT, CONJ, 1>(a, s) : go_tw<C, LOWER, UNIT, CONJ, 2>(a, s);
 }
 
 template <int C>
@@ -184,9 +223,14 @@ static hipError_t dispatch(bool lower, bool unit, bool conj, const TrsmArgs &a, 
 }
 
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
-                       ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s) {
+                       ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s,
+                       const int32_t *swl, int swstride) {
   if (nb <= 0 || ncols <= 0) return hipSuccess;
   if (nb > 64) {
+    if (swl) {
+      hipError_t e = launch_laswp_list(C, Xm, c0, ncols, swl, swstride, s);
+      if (e != hipSuccess) return e;
+    }
     // one row per lane: split op(T) into halves,
     //   lower op:  X1 = T11^-1 X1;  X2 -= T21 X1;  X2 = T22^-1 X2
     //   upper op:  X2 = T22^-1 X2;  X1 -= T12 X2;  X1 = T11^-1 X1
@@ -217,11 +261,15 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
   a.x0 = x0;
   a.c0 = c0;
   a.ncols = ncols;
-  // columns per workgroup: a multiple of the 8 the four waves take per pass, enough to
-  // spread over about 256 workgroups
+  a.swl = swl;
+  a.swstride = swstride;
+  // columns per workgroup: a multiple of the 8 the four waves take per pass (two columns
+  // each), enough to spread over about 256 workgroups; strips of at most 256 columns take
+  // 4 columns per workgroup, one per wave
   int64_t nbc = (a.ncols + 255) / 256;
   nbc = (nbc + 7) / 8 * 8;
   a.nbc = (int)(nbc < 8 ? 8 : nbc);
+  if (a.ncols <= 256) a.nbc = 4;
   switch (C) {
     case 2: return dispatch<2>(lower, unit, conj, a, s);
     case 3: return dispatch<3>(lower, unit, conj, a, s);
