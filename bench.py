@@ -128,7 +128,9 @@ def gemm_roofline(mp, torch, A0, panel, method):
     launches = []
     for j in range(0, n - panel, panel):
         r = n - j - panel
-        if r <= 0:
+        # products with fewer than 512 tiles of 32 x 32 go to the 16 x 16 kernel; the
+        # replay covers the launches of the 32 x 32 kernel, the dominant one
+        if r <= 0 or ((r + 31) // 32) ** 2 < 512:
             break
         launches.append((j, r))
     # warm up the kernel once
@@ -154,7 +156,7 @@ def gemm_roofline(mp, torch, A0, panel, method):
     flops = macs * real_per_complex * FLOPS_PER_REAL_MAC[C]
     achieved = flops / (total_ms / 1e3) / 1e12
     return {
-        "kernel": f"k_gemm<{C},{'3M' if method == '3m' else '4M'}> trailing update",
+        "kernel": f"k_gemm<{C},{'3M' if method == '3m' else '4M'},32x32 tiles> trailing update",
         "bound": "alu",
         "achieved": round(achieved, 3),
         "peak": PEAK_FP64_TFLOPS,
@@ -165,6 +167,55 @@ def gemm_roofline(mp, torch, A0, panel, method):
         "avg_launch_ms": round(total_ms / len(launches), 4),
         "flops_per_launch": flops / len(launches),
     }
+
+
+INT8_PEAK_TOPS = 5000.0  # MI355X dense INT8 MFMA
+
+
+def split_roofline(mp, torch, A0, panel, n_launch=12):
+    """MFMA rate of the INT8 split trailing update (DD, S = 17 slices): the first n_launch
+    trailing updates of one factorisation with panel width `panel`, each (slicing and
+    product kernels) bracketed by HIP events on the stream.  Counted work: the digit-pair
+    MFMAs, S (S + 1) / 2 pairs per 64-deep chunk, for each of the three real products."""
+    C, n = A0.shape[1], A0.shape[2]
+    M = A0.clone()
+    L = mp.lib()
+    ld, ps = n, n * n
+    base = M.data_ptr()
+    stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    S = 17
+    opts = mp._opts(panel, "split_i8")
+    nb = ct.c_size_t()
+    r0 = n - panel
+    assert L.mplu_zgemm_wsbytes(C, r0, r0, panel, 3, ct.byref(opts), ct.byref(nb)) == 0
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+
+    def sub(i, j):
+        return mp.ZMat(base + 8 * (j * ld + i), ld, ps)
+
+    launches = [(j, n - j - panel) for j in range(0, panel * n_launch, panel)]
+    evs = []
+    for it, (j, r) in enumerate([launches[0]] + launches):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rc = L.mplu_zgemm(C, b"N", b"N", r, r, panel, -1, sub(j + panel, j), sub(j, j + panel), 1,
+                          sub(j + panel, j + panel), 3, ct.byref(opts), work.data_ptr(),
+                          work.numel(), stream)
+        e1.record()
+        assert rc == 0, rc
+        if it > 0:
+            evs.append((e0, e1))
+    torch.cuda.synchronize()
+    total_ms = sum(a.elapsed_time(b) for a, b in evs)
+    kpad = (panel + 63) // 64 * 64
+    ops = sum(3 * (S * (S + 1) // 2) * 2 * r * r * kpad for (_, r) in launches)
+    achieved = ops / (total_ms / 1e3) / 1e12
+    return {"kernel": "k_slice + k_split_i8<2,17> (DD split INT8 trailing update)",
+            "bound": "mfma", "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
+            "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
+            "launches": len(launches), "avg_launch_ms": round(total_ms / len(launches), 4),
+            "panel": panel}
 
 
 def committed_traffic(kernel_src):
@@ -254,6 +305,9 @@ def main():
     if not args.no_roofline:
         line["roofline"] = gemm_roofline(mp, torch, A0, panel, method)
         print(f"[bench] roofline {line['roofline']}", file=sys.stderr, flush=True)
+    if not args.no_roofline:
+        line["roofline_split_i8"] = split_roofline(mp, torch, A0, 128)
+        print(f"[bench] split roofline {line['roofline_split_i8']}", file=sys.stderr, flush=True)
     if not args.no_variants:
         var = {}
         runs = ((2, "4m", panel, 2), (2, "3m", 128, 2), (2, "split_i8", 128, 2),
