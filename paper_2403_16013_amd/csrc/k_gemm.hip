@@ -297,19 +297,20 @@ static hipError_t go(const GemmArgs &a, hipStream_t s) {
 }
 
 // tile configurations for double-double (index selectable through MPLU_GEMM_CFG while
-// tuning); the default is entry 0
+// tuning); the default, entry 0, unrolls the k loop by two, which lets the level
+// accumulators stay in place across iterations instead of being copied at the back edge
 template <bool M3>
 static hipError_t go_dd(int cfg, const GemmArgs &a, hipStream_t s) {
   switch (cfg) {
     case 1: return go<2, M3, 64, 32, 8, 4, 2, 1>(a, s);
     case 2: return go<2, M3, 64, 64, 8, 4, 4, 1>(a, s);
     case 3: return go<2, M3, 32, 64, 8, 2, 4, 1>(a, s);
-    case 4: return go<2, M3, 32, 32, 8, 2, 2, 2>(a, s);
+    case 4: return go<2, M3, 32, 32, 8, 2, 2, 1>(a, s);
     case 5: return go<2, M3, 64, 32, 8, 4, 2, 2>(a, s);
     case 6: return go<2, M3, 64, 64, 16, 4, 2, 1>(a, s);
     case 7: return go<2, M3, 64, 64, 8, 2, 2, 1>(a, s);
-    case 8: return go<2, M3, 32, 32, 16, 2, 2, 1>(a, s);
-    default: return go<2, M3, 32, 32, 8, 2, 2, 1>(a, s);
+    case 8: return go<2, M3, 32, 32, 16, 2, 2, 2>(a, s);
+    default: return go<2, M3, 32, 32, 8, 2, 2, 2>(a, s);
   }
 }
 
@@ -344,7 +345,7 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
   const bool small = ((m + 31) / 32) * ((n + 31) / 32) < 512;
   switch (C) {
     case 2:
-      if (small) return m3 ? go<2, true, 16, 16, 16, 1, 1, 1>(a, s) : go<2, false, 16, 16, 16, 1, 1, 1>(a, s);
+      if (small) return m3 ? go<2, true, 16, 16, 16, 1, 1, 2>(a, s) : go<2, false, 16, 16, 16, 1, 1, 2>(a, s);
       return m3 ? go_dd<true>(gemm_cfg(), a, s) : go_dd<false>(gemm_cfg(), a, s);
     case 3:
       if (small) return m3 ? go<3, true, 16, 16, 16, 1, 1, 1>(a, s) : go<3, false, 16, 16, 16, 1, 1, 1>(a, s);

@@ -609,19 +609,25 @@ __global__ __launch_bounds__(256) void k_laswp(ZM A, int64_t c0, int64_t c1, int
   const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t ncols = c0 + (n - c1);
-  if (w >= ncols || cnt == 0) return;
+  if (w >= ncols) return;
   const int64_t col = w < c0 ? w : c1 + (w - c0);
   constexpr int Q = 2 * C;
-  // every read before any write, so the loads of all planes are in flight together
-  const int nh = (cnt + 63) / 64;  // at most 4 (cnt <= 2 kb <= 256)
+  // every read before any write, so the loads of all planes are in flight together; the
+  // list (2 kb slots per half) is read in the same round trip as its count
   double *col0 = A.p + col * A.ld;
   double v[4][Q];
   int32_t sr[4], ds[4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
     const int e = lane + 64 * h;
-    sr[h] = (h < nh && e < cnt) ? src[e] : -1;
-    ds[h] = (h < nh && e < cnt) ? dst[e] : -1;
+    sr[h] = e < 2 * kb ? src[e] : -1;
+    ds[h] = e < 2 * kb ? dst[e] : -1;
+  }
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const bool live = lane + 64 * h < cnt;
+    sr[h] = live ? sr[h] : -1;
+    ds[h] = live ? ds[h] : -1;
   }
 #pragma unroll
   for (int h = 0; h < 4; ++h)

@@ -70,14 +70,22 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   if (a.swl) {
     // row interchanges of this workgroup's columns, one column per wave at a time: every
     // read of a column before any write to it (at most 256 pairs)
+    // the count and both halves of the list are read together (the list has swstride
+    // slots per half), then masked by the count
     const int cnt = a.swl[0];
     const int32_t *dst = a.swl + 1, *src = a.swl + 1 + a.swstride;
     int32_t sr[4], ds[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int e = lane + 64 * h;
-      sr[h] = e < cnt ? src[e] : -1;
-      ds[h] = e < cnt ? dst[e] : -1;
+      sr[h] = e < a.swstride ? src[e] : -1;
+      ds[h] = e < a.swstride ? dst[e] : -1;
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const bool live = lane + 64 * h < cnt;
+      sr[h] = live ? sr[h] : -1;
+      ds[h] = live ? ds[h] : -1;
     }
     for (int cc = w; cc < ncl; cc += 4) {
       double *col0 = a.X.p + (cb + cc) * a.X.ld;
@@ -95,25 +103,37 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
     __syncthreads();
   }
 
-  for (int e = t; e < ntri; e += 256) {
-    int i, r;
-    if (LOWER) {  // column i has nb-1-i entries
-      i = 0;
-      int acc = 0;
-      while (acc + (nb - 1 - i) <= e) { acc += nb - 1 - i; ++i; }
-      r = i + 1 + (e - acc);
-    } else {      // column i has i entries
-      i = 1;
-      int acc = 0;
-      while (acc + i <= e) { acc += i; ++i; }
-      r = e - acc;
-    }
-    double tr[C], ti[C];
-    ld_opT<C, CONJ>(a, r, i, tr, ti);
+  // strict triangle, column by column: wave w takes columns w, w + 4, ...; lane = row.
+  // Eight columns' loads are issued before their LDS stores.
+  constexpr int SB = 8;
+  for (int i0 = w; i0 < nb; i0 += 4 * SB) {
+    double tv[SB][Q];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-      sT[(size_t)c * ntri + e] = tr[c];
-      sT[(size_t)(C + c) * ntri + e] = ti[c];
+    for (int u = 0; u < SB; ++u) {
+      const int i = i0 + 4 * u;
+      const bool in = i < nb && (LOWER ? (lane > i && lane < nb) : (lane < i));
+      double tr[C], ti[C];
+      if (in) {
+        ld_opT<C, CONJ>(a, lane, i, tr, ti);
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) tr[c] = ti[c] = 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        tv[u][c] = tr[c];
+        tv[u][C + c] = ti[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int i = i0 + 4 * u;
+      const bool in = i < nb && (LOWER ? (lane > i && lane < nb) : (lane < i));
+      if (in) {
+        const int off = col_off(i) + (LOWER ? lane - i - 1 : lane);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) sT[(size_t)q * ntri + off] = tv[u][q];
+      }
     }
   }
   if (!UNIT) {
