@@ -124,6 +124,24 @@ struct SplitArgs {
   int alpha, beta;
 };
 
+// Output tile of this workgroup in a 1-D grid of gm x gn tiles.  Workgroups are
+// dispatched round-robin over the 8 XCDs; the remap gives each XCD a contiguous range of
+// the tile order, and that order walks 8 tile rows down before moving one tile column
+// right, so the workgroups an XCD runs together share their rows and columns of the
+// digit planes in its L2.
+__device__ __forceinline__ void xcd_tile(int64_t gm, int64_t gn, int64_t &tm, int64_t &tn) {
+  constexpr int64_t NX = 8, GR = 8;
+  const int64_t total = gm * gn, L = blockIdx.x;
+  const int64_t full = total / NX * NX;
+  const int64_t id = L < full ? (L % NX) * (total / NX) + L / NX : L;
+  const int64_t gsz_all = GR * gn;
+  const int64_t grp = id / gsz_all, first = grp * GR;
+  const int64_t gsz = (gm - first) < GR ? gm - first : GR;
+  const int64_t in = id - grp * gsz_all;
+  tm = first + in % gsz;
+  tn = in / gsz;
+}
+
 // weights of the three real products in the real / imaginary parts
 __device__ __forceinline__ void op_signs(int op, double &sr, double &si) {
   sr = (op == 0) ? 1.0 : (op == 1 ? -1.0 : 0.0);
@@ -152,17 +170,30 @@ __device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t
 
 // INT8 digits, W = 7.  Workgroup: 4 waves, a 32 x 32 output tile; each wave a 16 x 16
 // block.  For each real product and each 64-deep k chunk the workgroup stages the S digit
-// planes of its 32 rows and 32 columns in LDS (16-byte coalesced loads, shared by the four
+// planes of its 32 rows and 32 columns in LDS (16 bytes per lane, shared by the four
 // waves); each wave then holds the S row fragments and S column fragments of its block in
 // registers and issues one MFMA per digit pair p + q <= S - 1 (0-based) into the level
 // accumulator of that pair: all pairs of one level share it.
+//
+// DB (two staging buffers fit in LDS, i.e. DD): the planes of the next chunk are loaded
+// straight into the other buffer (global-to-LDS, one 16-byte piece per lane at the wave's
+// base + 16 x lane) while the current chunk's MFMAs run.  Rows and columns past the edge
+// load the last valid one: they only reach outputs that are never stored.
+template <int S>
+__host__ __device__ constexpr bool split_i8_db() {
+  return 4 * S * 32 * 4 * 16 <= 160 * 1024;
+}
+
 template <int C, int S>
 __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   constexpr int W = 7;
-  extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes]
-  v4i *sX = sdig, *sY = sdig + S * 32 * 4;
+  constexpr bool DB = split_i8_db<S>();
+  constexpr int PL = S * 32 * 4;            // 16-byte pieces per operand per chunk
+  extern __shared__ v4i sdig[];             // [DB ? 2 : 1][2][S][32 rows][4 x 16 bytes]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t M0 = (int64_t)blockIdx.y * 32, N0 = (int64_t)blockIdx.x * 32;
+  int64_t tm, tn;
+  xcd_tile((g.m + 31) / 32, (g.n + 31) / 32, tm, tn);
+  const int64_t M0 = tm * 32, N0 = tn * 32;
   const int64_t m0 = M0 + 16 * (w >> 1), n0 = N0 + 16 * (w & 1);
   const int64_t bcol = n0 + (lane & 15);
   const int frow = 16 * (w >> 1) + (lane & 15), fcol = 16 * (w & 1) + (lane & 15);
@@ -174,6 +205,90 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
 #pragma unroll
     for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
 
+  if constexpr (DB) {
+    // the exponent sums of this lane's four outputs for the three products, fetched up
+    // front so the per-product flush does not wait on memory
+    int tsums[3][4];
+#pragma unroll
+    for (int op = 0; op < 3; ++op)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
+        tsums[op][e] = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
+                       (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
+      }
+    const int nck = (int)(g.Kpad / 64);
+    const int total = 3 * nck;  // (product, chunk) pairs in order
+    // piece e = (plane p, row r, quarter f) of chunk `it` into buffer `buf`
+    auto issue = [&](int it, int buf) {
+      const int op = it / nck;
+      const int64_t kc = (int64_t)(it % nck) * 64;
+      const int8_t *xo = xs + (int64_t)op * S * g.m * g.Kpad;
+      const int8_t *yo = ys + (int64_t)op * S * g.n * g.Kpad;
+      v4i *dX = sdig + (size_t)buf * 2 * PL, *dY = dX + PL;
+      for (int e0 = w * 64; e0 < PL; e0 += 256) {
+        const int e = e0 + lane;
+        const int f = e & 3, r = (e >> 2) & 31, pl = e >> 7;
+        const int64_t gi = (M0 + r < g.m) ? M0 + r : g.m - 1;
+        const int64_t gj = (N0 + r < g.n) ? N0 + r : g.n - 1;
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(xo + ((int64_t)pl * g.m + gi) * g.Kpad + kc + 16 * f),
+            (__attribute__((address_space(3))) void *)(dX + e0), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(yo + ((int64_t)pl * g.n + gj) * g.Kpad + kc + 16 * f),
+            (__attribute__((address_space(3))) void *)(dY + e0), 16, 0, 0);
+      }
+    };
+    issue(0, 0);
+    for (int op = 0; op < 3; ++op) {
+      double sr, si;
+      op_signs(op, sr, si);
+      v4i acc[S];
+#pragma unroll
+      for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
+      for (int c = 0; c < nck; ++c) {
+        const int it = op * nck + c;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces of chunk it have landed
+        __syncthreads();                // and everybody else's
+        if (it + 1 < total) issue(it + 1, (it + 1) & 1);
+        const v4i *sX = sdig + (size_t)(it & 1) * 2 * PL, *sY = sX + PL;
+        v4i a[S], b[S];
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          a[p] = sX[(p * 32 + frow) * 4 + fk];
+          b[p] = sY[(p * 32 + fcol) * 4 + fk];
+        }
+#pragma unroll
+        for (int p = 0; p < S; ++p)
+#pragma unroll
+          for (int q = 0; q < S - p; ++q)
+            acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
+        __syncthreads();  // this buffer is refilled two chunks later
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int tsum = tsums[0][e];
+#pragma unroll
+        for (int o = 1; o < 3; ++o) tsum = (op == o) ? tsums[o][e] : tsum;
+#pragma unroll
+        for (int top = S - 1; top >= 0; top -= 4) {
+          const int lo = top - 3 < 0 ? 0 : top - 3;
+          double grp = 0.0;
+#pragma unroll
+          for (int l = top; l >= lo; --l)
+            grp = __builtin_fma((double)acc[l][e], ldexp(1.0, (lo - l) * W), grp);
+          grp = ldexp(grp, tsum - (lo + 2) * W);
+          if (sr != 0.0) mp::push<C>(lr[e], 0, sr * grp);
+          mp::push<C>(li[e], 0, si * grp);
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) epilogue<C>(g, m0 + 4 * (lane >> 4) + e, bcol, lr[e], li[e]);
+    return;
+  }
+
+  v4i *sX = sdig, *sY = sdig + PL;
   for (int op = 0; op < 3; ++op) {
     double sr, si;
     op_signs(op, sr, si);
@@ -337,7 +452,7 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
   g.Cm = Cm; g.ci = ci; g.cj = cj; g.alpha = alpha; g.beta = beta;
   const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
   if constexpr (I8) {
-    const size_t lds = sizeof(v4i) * 2 * S * 32 * 4;
+    const size_t lds = sizeof(v4i) * (split_i8_db<S>() ? 4 : 2) * S * 32 * 4;
     static bool attr = false;
     if (!attr) {
       hipError_t e = hipFuncSetAttribute((const void *)k_split_i8<C, S>,
@@ -345,7 +460,8 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
       if (e != hipSuccess) return e;
       attr = true;
     }
-    hipLaunchKernelGGL((k_split_i8<C, S>), grid, dim3(256), lds, s, g);
+    const dim3 grid1((unsigned)(((n + 31) / 32) * ((m + 31) / 32)));
+    hipLaunchKernelGGL((k_split_i8<C, S>), grid1, dim3(256), lds, s, g);
   } else {
     hipLaunchKernelGGL((k_split_f64<C, S>), grid, dim3(256), 0, s, g);
   }
