@@ -42,6 +42,24 @@ __device__ __forceinline__ void st_z(const ZM &A, int64_t i, int64_t j, const do
   }
 }
 
+// Output tile of this workgroup in a 1-D grid of gm x gn tiles.  Workgroups are
+// dispatched round-robin over the 8 XCDs; the remap gives each XCD a contiguous range of
+// the tile order, and that order walks 8 tile rows down before moving one tile column
+// right, so the workgroups an XCD runs together share their rows and columns of the
+// operands in its L2.
+__device__ __forceinline__ void xcd_tile(int64_t gm, int64_t gn, int64_t &tm, int64_t &tn) {
+  constexpr int64_t NX = 8, GR = 8;
+  const int64_t total = gm * gn, L = blockIdx.x;
+  const int64_t full = total / NX * NX;
+  const int64_t id = L < full ? (L % NX) * (total / NX) + L / NX : L;
+  const int64_t gsz_all = GR * gn;
+  const int64_t grp = id / gsz_all, first = grp * GR;
+  const int64_t gsz = (gm - first) < GR ? gm - first : GR;
+  const int64_t in = id - grp * gsz_all;
+  tm = first + in % gsz;
+  tn = in / gsz;
+}
+
 // ------------------------------------------------------------------ launcher interface
 // Every launcher validates nothing (the C ABI does) and returns the launch status.
 

@@ -39,7 +39,9 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
 
   const int tid = threadIdx.x;
   const int tx = tid % SX, ty = tid / SX;
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  int64_t tm, tn;
+  xcd_tile((g.m + BM - 1) / BM, (g.n + BN - 1) / BN, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
 
   // accumulators
   double acc[NV][TM][TN][C];
@@ -291,7 +293,7 @@ static hipError_t go_narrow(const GemmArgs &a, hipStream_t s) {
 template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR>
 static hipError_t go(const GemmArgs &a, hipStream_t s) {
   constexpr int NT = (BM / TM) * (BN / TN);
-  const dim3 grid((unsigned)((a.n + BN - 1) / BN), (unsigned)((a.m + BM - 1) / BM));
+  const dim3 grid((unsigned)(((a.n + BN - 1) / BN) * ((a.m + BM - 1) / BM)));
   hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN, UNR>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
