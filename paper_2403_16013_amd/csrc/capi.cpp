@@ -73,9 +73,10 @@ inline bool split_opts_ok(int C, int method, const mplu_opts_t *o) {
   return split_supported(C, i8, S);
 }
 
-// getrf workspace: two panel workspaces (consecutive panels alternate, so the step-k
-// interchanges stay readable while panel k+1 is factored), then for the split methods one
-// slice workspace for the rest of the trailing matrix and one for the next panel's columns
+// getrf workspace: three panel workspaces (consecutive panels rotate through them, so the
+// step-k interchanges stay readable until the second stream has applied them to the
+// columns left of the panel), then for the split methods one slice workspace for the rest
+// of the trailing matrix and one for the next panel's columns
 struct GetrfWS {
   size_t panel, split_rest, split_next, total;
 };
@@ -94,7 +95,7 @@ GetrfWS getrf_layout(int C, int64_t m, int64_t n, const mplu_opts_t *o) {
     w.split_rest = align256(split_ws_bytes(C, i8, m, n, kb, S));
     w.split_next = align256(split_ws_bytes(C, i8, m, kb, kb, S));
   }
-  w.total = 2 * w.panel + w.split_rest + w.split_next;
+  w.total = 3 * w.panel + w.split_rest + w.split_next;
   return w;
 }
 
@@ -236,14 +237,13 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   const ZM a = zm(A);
   const GetrfWS L = getrf_layout(C, m, n, opts);
   char *wb = (char *)d_work;
-  void *pws[2] = {wb, wb + L.panel};
-  void *split_rest = wb + 2 * L.panel;
-  void *split_next = wb + 2 * L.panel + L.split_rest;
+  void *pws[3] = {wb, wb + L.panel, wb + 2 * L.panel};
+  void *split_rest = wb + 3 * L.panel;
+  void *split_next = wb + 3 * L.panel + L.split_rest;
   const int S = opts ? opts->n_slices : 0;
 
-  unsigned base[2] = {0u, 0u};
-  HIPCHK(panel_ws_clear(pws[0], s));
-  HIPCHK(panel_ws_clear(pws[1], s));
+  unsigned base[3] = {0u, 0u, 0u};
+  for (int i = 0; i < 3; ++i) HIPCHK(panel_ws_clear(pws[i], s));
   if (opts && (opts->flags & MPLU_FLAG_NO_LOOKAHEAD)) {
     for (int64_t j = 0; j < mn; j += kb) {
       const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
@@ -257,10 +257,11 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   // Look-ahead by one panel.  After panel k (columns [j, j+jb)) is factored:
   //   caller's stream:  interchanges, U12 and A22 update of the next panel's columns,
   //                     then panel k+1;
-  //   second stream:    interchanges of the columns left of the panel and right of the
-  //                     next panel, then their U12 / A22 update.
+  //   second stream:    interchanges and U12 of the columns right of the next panel, their
+  //                     A22 update, then the interchanges of the columns left of panel k
+  //                     (nothing reads those before the end).
   // The next panel's columns are up to date through step k-1 only after the second
-  // stream's step k-1, which the caller's stream waits for first.
+  // stream's step k-1 product, which the caller's stream waits for first.
   std::lock_guard<std::mutex> lock(g_side_mu);
   SideStream *sd = side_stream();
   if (!sd) return MPLU_E_HIP;
@@ -269,13 +270,12 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   int k = 0;
   for (int64_t j = 0; j < mn; j += kb, ++k) {
     const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
-    void *pw = pws[k & 1];
+    void *pw = pws[k % 3];
     const int64_t nx0 = j + jb;  // next panel's columns [nx0, nx1)
     const int64_t nx1 = nx0 < mn ? nx0 + ((mn - nx0) < kb ? (mn - nx0) : kb) : nx0;
     HIPCHK(hipEventRecord(sd->ev_panel, s));
     if (k > 0) HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));
     HIPCHK(hipStreamWaitEvent(b, sd->ev_panel, 0));
-    HIPCHK(launch_laswp(C, a, j, nx1, n, pw, jb, b));
     if (nx1 > nx0) {
       // the next panel's columns: interchanges and U12 in one launch, then the product
       HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb)));
@@ -284,14 +284,19 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device
     HIPCHK(hipEventRecord(sd->ev_chain, s));
-    HIPCHK(step_trsm(C, a, j, jb, nx1, n, b));
+    HIPCHK(step_trsm(C, a, j, jb, nx1, n, b, panel_swap_list(pw, C, jb)));
     HIPCHK(hipStreamWaitEvent(b, sd->ev_chain, 0));
     HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx1, n, split_rest, b));
     HIPCHK(hipEventRecord(sd->ev_rest, b));
+    // panel k's interchanges on the columns left of it; the workspace holding the list is
+    // next written by panel k+3, which the caller's stream starts only after the second
+    // stream's step k+1 product
+    HIPCHK(launch_laswp(C, a, j, n, n, pw, jb, b));
     if (nx1 > nx0)
-      HIPCHK(launch_panel(C, a, nx0, m, (int)(nx1 - nx0), d_ipiv, d_info, pws[(k + 1) & 1],
-                          &base[(k + 1) & 1], s));
+      HIPCHK(launch_panel(C, a, nx0, m, (int)(nx1 - nx0), d_ipiv, d_info, pws[(k + 1) % 3],
+                          &base[(k + 1) % 3], s));
   }
+  HIPCHK(hipEventRecord(sd->ev_rest, b));
   HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));
   return 0;
 }

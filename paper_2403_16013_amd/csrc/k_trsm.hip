@@ -284,9 +284,9 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
   a.swl = swl;
   a.swstride = swstride;
   // columns per workgroup: a multiple of the 8 the four waves take per pass (two columns
-  // each), enough to spread over about 256 workgroups; strips of at most 256 columns take
-  // 4 columns per workgroup, one per wave
-  int64_t nbc = (a.ncols + 255) / 256;
+  // each), enough to spread over about 512 workgroups (two per CU for double-double);
+  // strips of at most 256 columns take 4 columns per workgroup, one per wave
+  int64_t nbc = (a.ncols + 511) / 512;
   nbc = (nbc + 7) / 8 * 8;
   a.nbc = (int)(nbc < 8 ? 8 : nbc);
   if (a.ncols <= 256) a.nbc = 4;

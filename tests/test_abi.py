@@ -56,6 +56,14 @@ def test_argument_checks(L):
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
     bad = m.Opts(64, 9, 0, 0, 0)
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
+    # flags: only MPLU_FLAG_NO_LOOKAHEAD (1) is defined
+    for flags in (2, 4, 1 | 8, -1):
+        bad = m.Opts(64, 1, 0, 0, flags)
+        assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
+        assert L.mplu_zgesv(2, 8, 1, z, ip, z, inf, ct.byref(bad), wk, 1 << 30, None) == -8
+    assert m.FLAG_NO_LOOKAHEAD == 1
+    assert re.search(r"#define\s+MPLU_FLAG_NO_LOOKAHEAD\s+1\b",
+                     open(os.path.join(ROOT, "include", "mplu.h")).read())
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, None, ct.c_void_p(0x10001), 1 << 30, None) == -8
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, None, wk, 16, None) == -100
     assert L.mplu_zgetrs(2, b"X", 8, 1, z, ip, z, wk, 1 << 30, None) == -2
@@ -79,6 +87,14 @@ def test_workspace_queries(L):
     o = m.Opts(128, 1, 0, 0, 0)
     assert L.mplu_zgetrf_wsbytes(4, 4096, 4096, ct.byref(o), ct.byref(sz)) == 0
     assert sz.value > a > 0
+    # the split methods add slice workspaces for the rest and for the next panel's columns
+    o3 = m.Opts(128, 3, 0, 0, 0)
+    assert L.mplu_zgetrf_wsbytes(2, 4096, 4096, ct.byref(o3), ct.byref(sz)) == 0
+    i8 = sz.value
+    assert i8 > a
+    g = ct.c_size_t()
+    assert L.mplu_zgemm_wsbytes(2, 4096, 4096, 128, 3, ct.byref(o3), ct.byref(g)) == 0
+    assert i8 >= g.value
     assert L.mplu_zgetrs_wsbytes(2, 100, 3, ct.byref(sz)) == 0
     assert sz.value >= 100 * 3 * 4 * 8
     assert L.mplu_zgesv_wsbytes(3, 100, 3, None, ct.byref(sz)) == 0
