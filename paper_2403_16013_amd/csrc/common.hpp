@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "mp.hpp"
 
 #pragma clang fp contract(off)
@@ -59,6 +61,21 @@ __device__ __forceinline__ void xcd_tile(int64_t gm, int64_t gn, int64_t &tm, in
   tm = first + in % gsz;
   tn = in / gsz;
 }
+
+// Raise a kernel's dynamic-LDS limit once per device (thread-safe; a failed attempt is
+// retried on the next launch).  One static instance per kernel.
+struct LdsAttr {
+  std::atomic<int> done[64];
+  hipError_t ensure(const void *kernel, int bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (done[dev].load(std::memory_order_acquire)) return hipSuccess;
+    const hipError_t e =
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) done[dev].store(1, std::memory_order_release);
+    return e;
+  }
+};
 
 // ------------------------------------------------------------------ launcher interface
 // Every launcher validates nothing (the C ABI does) and returns the launch status.

@@ -317,8 +317,11 @@ static hipError_t go_dd(int cfg, const GemmArgs &a, hipStream_t s) {
 }
 
 static int gemm_cfg() {
-  const char *e = getenv("MPLU_GEMM_CFG");
-  return e ? atoi(e) : 0;
+  static const int cfg = [] {
+    const char *e = getenv("MPLU_GEMM_CFG");
+    return e ? atoi(e) : 0;
+  }();
+  return cfg;
 }
 
 hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,

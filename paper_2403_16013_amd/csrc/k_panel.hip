@@ -73,15 +73,15 @@ static inline size_t panel_lds(int C, int kb, int R) {
 
 // compute units of the current device (the panel's workgroups must all be resident)
 static int device_cus() {
-  static int cus[64] = {0};
+  static std::atomic<int> cus[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cus[dev] == 0) {
-    int v = 0;
+  int v = cus[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    cus[dev] = v;
+    cus[dev].store(v, std::memory_order_relaxed);
   }
-  return cus[dev];
+  return v;
 }
 
 PanelGeom panel_geometry(int C, int64_t mp, int kb) {
@@ -92,12 +92,12 @@ PanelGeom panel_geometry(int C, int64_t mp, int kb) {
   while (rmax > 1 && panel_lds(C, kb, rmax) > PLDS_BUDGET) --rmax;
   // aim for about 96 workgroups: fewer makes the per-column barrier cheaper, more
   // spreads the rank-1 work; never below 8 rows each
-  static int target = 0;
-  if (target == 0) {
+  // (MPLU_PANEL_WGS overrides the target, for tuning)
+  static const int target = [] {
     const char *e = getenv("MPLU_PANEL_WGS");
-    target = e ? atoi(e) : 96;
-    if (target < 1) target = 96;
-  }
+    const int t = e ? atoi(e) : 96;
+    return t < 1 ? 96 : t;
+  }();
   int64_t R = (mp + target - 1) / target;
   if (R < 8) R = 8;
   if (R > rmax) R = rmax;
@@ -657,14 +657,9 @@ static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ip
   a.w = carve(ws, C, kb, nullptr);
   a.base = *base;
   *base += (unsigned)geo.G * (unsigned)kb;
-  static bool attr_done[5] = {false, false, false, false, false};
-  if (!attr_done[C]) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_panel<C>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)PLDS_BUDGET);
-    if (e != hipSuccess) return e;
-    attr_done[C] = true;
-  }
+  static LdsAttr attr;
+  const hipError_t ae = attr.ensure((const void *)k_panel<C>, (int)PLDS_BUDGET);
+  if (ae != hipSuccess) return ae;
   // G never exceeds the CU count and one workgroup fits a CU, so every workgroup becomes
   // resident once the kernels sharing the device retire theirs: an ordinary launch
   // suffices, and it may run beside the trailing update on another stream

@@ -435,13 +435,9 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
   const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
   if constexpr (I8) {
     const size_t lds = sizeof(v4i) * (split_i8_db<S>() ? 4 : 2) * S * 32 * 4;
-    static bool attr = false;
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute((const void *)k_split_i8<C, S>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    static LdsAttr attr;
+    const hipError_t e = attr.ensure((const void *)k_split_i8<C, S>, (int)lds);
+    if (e != hipSuccess) return e;
     const dim3 grid1((unsigned)(((n + 31) / 32) * ((m + 31) / 32)));
     hipLaunchKernelGGL((k_split_i8<C, S>), grid1, dim3(256), lds, s, g);
   } else {

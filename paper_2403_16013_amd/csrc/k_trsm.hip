@@ -211,13 +211,9 @@ template <int C, bool LOWER, bool UNIT, bool CONJ, int TW>
 static hipError_t go_tw(const TrsmArgs &a, hipStream_t s) {
   constexpr int Q = 2 * C;
   const size_t lds = sizeof(double) * ((size_t)a.nb * Q + (size_t)Q * (a.nb * (a.nb - 1) / 2));
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_trsm<C, LOWER, UNIT, CONJ, TW>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static LdsAttr attr;
+  const hipError_t e = attr.ensure((const void *)k_trsm<C, LOWER, UNIT, CONJ, TW>, 160 * 1024);
+  if (e != hipSuccess) return e;
   const int64_t blocks = (a.ncols + a.nbc - 1) / a.nbc;
   hipLaunchKernelGGL((k_trsm<C, LOWER, UNIT, CONJ, TW>), dim3((unsigned)blocks), dim3(256), lds,
                      s, a);

@@ -313,13 +313,9 @@ template <int C, bool LOWER, bool UNIT, bool CONJ, int NR>
 static hipError_t go_sv(const SvArgs &a, hipStream_t s) {
   constexpr int Q = 2 * C;
   const size_t lds = sizeof(double) * ((size_t)5 * Q * NR * SVB + (size_t)2 * Q * SVCH * SVB);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_trsv<C, LOWER, UNIT, CONJ, NR>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static LdsAttr attr;
+  const hipError_t e = attr.ensure((const void *)k_trsv<C, LOWER, UNIT, CONJ, NR>, (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_trsv<C, LOWER, UNIT, CONJ, NR>), dim3((unsigned)(a.nblk * a.ngrp)),
                      dim3(256), lds, s, a);
   return hipGetLastError();
