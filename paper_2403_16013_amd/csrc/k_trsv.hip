@@ -15,8 +15,8 @@
 // first, so the chain always progresses; every wait is still bounded and an expired wait
 // turns the solution into NaN rather than hanging.
 //
-// Element operations: the 4M complex product (Eq. 4m), diagonal by reciprocal then
-// product, as in the blocked triangular solve.
+// Element operations: the 4M complex product (Eq. 4m); a non-unit diagonal is applied by
+// its reciprocal, to the rows of the block and of the right-hand side before the sweep.
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
   double *sx = smem;                          // [Q][NR][SVB]   published block being folded
   double *sp = sx + Q * NR * SVB;             // [4][Q][NR][SVB] per-wave partial sums
   double *sd = sp + 4 * Q * NR * SVB;         // [2][Q][SVCH][SVB] diagonal-block chunks
+  double *sRc = sd + 2 * Q * SVCH * SVB;      // [Q][SVB] reciprocals of the diagonal
   __shared__ int s_expired;
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -97,6 +98,21 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
       double re[C], im[C];
       if (row < nr && u < nr) {
         ld_op<C, CONJ>(T, r0 + row, r0 + col_of(u), re, im);
+        if (!UNIT) {
+          // row `row` of the block divided by its diagonal entry (by its reciprocal)
+          double rr[C], ri[C], orr[C], oi[C];
+#pragma unroll
+          for (int k = 0; k < C; ++k) {
+            rr[k] = sRc[k * SVB + row];
+            ri[k] = sRc[(C + k) * SVB + row];
+          }
+          mp::zmul<C>(re, im, rr, ri, orr, oi);
+#pragma unroll
+          for (int k = 0; k < C; ++k) {
+            re[k] = orr[k];
+            im[k] = oi[k];
+          }
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < C; ++k) re[k] = im[k] = 0.0;
@@ -110,17 +126,23 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
   };
 
   if (t == 0) s_expired = 0;
-  stage_chunk(0, 0, t, 256);
-
-  // reciprocal of this lane's diagonal entry (wave 0)
-  double rr[C], ri[C];
+  // Non-unit diagonal: every row of the block is divided by its diagonal entry up front
+  // (the staged block and, once formed, the right-hand side), so the sweep below needs no
+  // division on its chain of dependent steps.
+  if (!UNIT) {
+    if (w == 0 && lane < nr) {
+      double dr[C], di[C], rr[C], ri[C];
+      ld_op<C, CONJ>(T, r0 + lane, r0 + lane, dr, di);
+      mp::zrecip<C>(dr, di, rr, ri);
 #pragma unroll
-  for (int k = 0; k < C; ++k) rr[k] = ri[k] = 0.0;
-  if (!UNIT && w == 0 && lane < nr) {
-    double dr[C], di[C];
-    ld_op<C, CONJ>(T, r0 + lane, r0 + lane, dr, di);
-    mp::zrecip<C>(dr, di, rr, ri);
+      for (int k = 0; k < C; ++k) {
+        sRc[k * SVB + lane] = rr[k];
+        sRc[(C + k) * SVB + lane] = ri[k];
+      }
+    }
+    __syncthreads();
   }
+  stage_chunk(0, 0, t, 256);
 
   // ---- contributions of the blocks this one depends on
   double accR[NR][C], accI[NR][C];
@@ -240,6 +262,20 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
       }
       mp::renorm<C>(lr, yr[h]);
       mp::renorm<C>(li, yi[h]);
+      if (!UNIT && lane < nr) {
+        double rr[C], ri[C], orr[C], oi[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          rr[k] = sRc[k * SVB + lane];
+          ri[k] = sRc[(C + k) * SVB + lane];
+        }
+        mp::zmul<C>(yr[h], yi[h], rr, ri, orr, oi);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          yr[h][k] = orr[k];
+          yi[h][k] = oi[k];
+        }
+      }
     }
   }
 
@@ -250,18 +286,6 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
       const int ucount = (nr - c * SVCH) < SVCH ? nr - c * SVCH : SVCH;
       for (int uu = 0; uu < ucount; ++uu) {
         const int s = col_of(c * SVCH + uu);
-        if (!UNIT && lane == s) {
-#pragma unroll
-          for (int h = 0; h < NR; ++h) {
-            double orr[C], oi[C];
-            mp::zmul<C>(yr[h], yi[h], rr, ri, orr, oi);
-#pragma unroll
-            for (int k = 0; k < C; ++k) {
-              yr[h][k] = orr[k];
-              yi[h][k] = oi[k];
-            }
-          }
-        }
         double tr[C], ti[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
@@ -312,7 +336,8 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 template <int C, bool LOWER, bool UNIT, bool CONJ, int NR>
 static hipError_t go_sv(const SvArgs &a, hipStream_t s) {
   constexpr int Q = 2 * C;
-  const size_t lds = sizeof(double) * ((size_t)5 * Q * NR * SVB + (size_t)2 * Q * SVCH * SVB);
+  const size_t lds =
+      sizeof(double) * ((size_t)5 * Q * NR * SVB + (size_t)2 * Q * SVCH * SVB + (size_t)Q * SVB);
   static LdsAttr attr;
   const hipError_t e = attr.ensure((const void *)k_trsv<C, LOWER, UNIT, CONJ, NR>, (int)lds);
   if (e != hipSuccess) return e;

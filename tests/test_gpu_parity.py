@@ -389,3 +389,30 @@ def test_lookahead_repeated_calls_and_gesv(mp, orc):
         mp.gesv(T, Bd, panel=32, method="3m", work=work)
         sync()
         assert np.array_equal(to_host(T), ref[0]) and np.array_equal(to_host(Bd), ref[1])
+
+
+def test_lookahead_two_streams_concurrently(mp, orc):
+    """Two factorisations enqueued back to back on two different caller streams share the
+    library's second stream; each must still equal its in-order result."""
+    import torch
+
+    n, C = 300, 2
+    A1 = orc.canon(synthgen.uniform(n, n, C, 101))
+    A2 = orc.canon(synthgen.uniform(n, n, C, 102))
+    ref = []
+    for A in (A1, A2):
+        T = to_dev(A)
+        ipiv, _ = mp.getrf(T, panel=64, method="3m", lookahead=False)
+        sync()
+        ref.append((to_host(T), ipiv.cpu().numpy()))
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    T1, T2 = to_dev(A1), to_dev(A2)
+    sync()
+    with torch.cuda.stream(s1):
+        ip1, _ = mp.getrf(T1, panel=64, method="3m")
+    with torch.cuda.stream(s2):
+        ip2, _ = mp.getrf(T2, panel=64, method="3m")
+    sync()
+    for (R, rp), T, ip in zip(ref, (T1, T2), (ip1, ip2)):
+        assert np.array_equal(ip.cpu().numpy(), rp)
+        assert np.array_equal(to_host(T), R)
