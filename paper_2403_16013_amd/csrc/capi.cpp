@@ -324,7 +324,7 @@ int mplu_zgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_zmat_t LU,
   if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
   if (work_bytes < need) return MPLU_E_WORKSPACE;
   if (n == 0 || nrhs == 0) return 0;
-  if (n > 40960) return MPLU_E_UNSUPPORTED;
+  if (n > INT32_MAX) return MPLU_E_UNSUPPORTED;  // 1-based int32 pivot indices
   hipStream_t s = (hipStream_t)stream;
   const int C = prec;
   int32_t *perm = (int32_t *)d_work;

@@ -58,22 +58,30 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count) {
 
 // perm[k] = original row that ends up at row k after the interchanges of ipiv, applied in
 // order (one workgroup: the row index array lives in LDS while the swaps are replayed).
+// perm[i] = the original row that the interchanges ipiv[0..n) (applied in order, LAPACK
+// laswp semantics) bring to position i.  The interchange sequence is inherently serial,
+// but each original row's path through it is independent: thread r follows row r's
+// position through all n interchanges (ipiv staged in LDS in chunks, read by broadcast)
+// and finally records perm[position] = r.
+static constexpr int PERM_CHUNK = 8192;
+
 __global__ __launch_bounds__(1024) void k_perm(const int32_t *ipiv, int64_t n, int32_t *perm) {
-  extern __shared__ int32_t sp[];
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) sp[i] = (int32_t)i;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int64_t k = 0; k < n; ++k) {
-      const int32_t p = ipiv[k] - 1;
-      if (p != k && p >= 0 && p < n) {
-        const int32_t t = sp[k];
-        sp[k] = sp[p];
-        sp[p] = t;
-      }
+  __shared__ int32_t sp[PERM_CHUNK];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t pos = r;
+  for (int64_t k0 = 0; k0 < n; k0 += PERM_CHUNK) {
+    const int cnt = (int)((n - k0) < PERM_CHUNK ? (n - k0) : PERM_CHUNK);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) sp[i] = ipiv[k0 + i] - 1;
+    __syncthreads();
+    for (int i = 0; i < cnt; ++i) {
+      const int64_t k = k0 + i;
+      int64_t p = sp[i];
+      if (p < 0 || p >= n) p = k;  // an invalid entry swaps nothing
+      pos = (pos == k) ? p : ((pos == p) ? k : pos);
     }
   }
-  __syncthreads();
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) perm[i] = sp[i];
+  if (r < n) perm[pos] = (int32_t)r;
 }
 
 // gather: W[k, :] = B[perm[k], :];  scatter: B[perm[k], :] = W[k, :]
@@ -137,14 +145,7 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) 
 
 hipError_t launch_perm(const int32_t *ipiv, int64_t n, int32_t *perm, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = sizeof(int32_t) * (size_t)n;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_perm,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_perm, dim3(1), dim3(1024), lds, s, ipiv, n, perm);
+  hipLaunchKernelGGL(k_perm, dim3((unsigned)((n + 1023) / 1024)), dim3(1024), 0, s, ipiv, n, perm);
   return hipGetLastError();
 }
 
