@@ -151,63 +151,99 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
     for (int k = 0; k < C; ++k) accR[h][k] = accI[h][k] = 0.0;
 
+  // Each wave folds 16 columns of every block it depends on.  The matrix entries do not
+  // depend on the solution, so a batch of them is loaded before the wait for the block's
+  // ready word; their latency hides behind the wait.
+  constexpr int TB = (C == 2) ? 16 : 8;  // columns per batch (registers)
   const int ndep = LOWER ? ib : nblk - 1 - ib;
   for (int st = 0; st < ndep; ++st) {
     const int jb = LOWER ? st : nblk - 1 - st;
-    if (t == 0) {
-      const int32_t *f = ready + (size_t)jb * ngrp + grp;
-      unsigned spins = 0;
-      while (__hip_atomic_load(const_cast<int32_t *>(f), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if ((spins & 255u) == 255u &&
-            __hip_atomic_load(expiry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          s_expired = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > SV_SPIN_LIMIT) {
-          __hip_atomic_store(expiry, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s_expired = 1;
-          break;
-        }
-      }
-    }
-    __syncthreads();
-    if (s_expired) break;
     const int64_t j0 = (int64_t)jb * SVB;
     const int nj = (int)((n - j0) < SVB ? (n - j0) : SVB);
-    for (int e = t; e < Q * NR * SVB; e += 256) {
-      const int row = e % SVB, rest = e / SVB, h = rest % NR, q = rest / NR;
-      sx[e] = (row < nj && h < ncr) ? sv_get(X.p + (int64_t)q * X.ps + (x0 + h) * X.ld + j0 + row)
-                                    : 0.0;
-    }
-    __syncthreads();
-    if (lane < nr) {
-      const int cbeg = w * (SVB / 4);
-      const int cend = (cbeg + SVB / 4) < nj ? cbeg + SVB / 4 : nj;
-      for (int col = cbeg; col < cend; ++col) {
-        double tr[C], ti[C], ntr[C], nti[C];
-        ld_op<C, CONJ>(T, r0 + lane, j0 + col, tr, ti);
+    const int cbeg = w * (SVB / 4);
+#pragma unroll
+    for (int half = 0; half < (SVB / 4) / TB; ++half) {
+      double tv[TB][Q];
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+        const int col = cbeg + half * TB + u;
+        double tr[C], ti[C];
+        if (lane < nr && col < nj) {
+          ld_op<C, CONJ>(T, r0 + lane, j0 + col, tr, ti);
+        } else {
+#pragma unroll
+          for (int k = 0; k < C; ++k) tr[k] = ti[k] = 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-          ntr[k] = -tr[k];
-          nti[k] = -ti[k];
-        }
-#pragma unroll
-        for (int h = 0; h < NR; ++h) {
-          double xr[C], xi[C];
-#pragma unroll
-          for (int k = 0; k < C; ++k) {
-            xr[k] = sx[((size_t)k * NR + h) * SVB + col];
-            xi[k] = sx[((size_t)(C + k) * NR + h) * SVB + col];
-          }
-          // acc -= t x
-          mp::mac<C>(accR[h], ntr, xr);
-          mp::mac<C>(accR[h], ti, xi);
-          mp::mac<C>(accI[h], ntr, xi);
-          mp::mac<C>(accI[h], nti, xr);
+          tv[u][k] = tr[k];
+          tv[u][C + k] = ti[k];
         }
       }
+      if (half == 0) {
+        if (t == 0) {
+          const int32_t *f = ready + (size_t)jb * ngrp + grp;
+          unsigned spins = 0;
+          while (__hip_atomic_load(const_cast<int32_t *>(f), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if ((spins & 255u) == 255u &&
+                __hip_atomic_load(expiry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              s_expired = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SV_SPIN_LIMIT) {
+              __hip_atomic_store(expiry, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              s_expired = 1;
+              break;
+            }
+          }
+        }
+        __syncthreads();
+        if (!s_expired) {
+          for (int e = t; e < Q * NR * SVB; e += 256) {
+            const int row = e % SVB, rest = e / SVB, h = rest % NR, q = rest / NR;
+            sx[e] = (row < nj && h < ncr)
+                        ? sv_get(X.p + (int64_t)q * X.ps + (x0 + h) * X.ld + j0 + row)
+                        : 0.0;
+          }
+        }
+        __syncthreads();
+      }
+      if (s_expired) break;
+      if (lane < nr) {
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          const int col = cbeg + half * TB + u;
+          if (col < nj) {
+            double tr[C], ti[C], ntr[C], nti[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) {
+              tr[k] = tv[u][k];
+              ti[k] = tv[u][C + k];
+              ntr[k] = -tr[k];
+              nti[k] = -ti[k];
+            }
+#pragma unroll
+            for (int h = 0; h < NR; ++h) {
+              double xr[C], xi[C];
+#pragma unroll
+              for (int k = 0; k < C; ++k) {
+                xr[k] = sx[((size_t)k * NR + h) * SVB + col];
+                xi[k] = sx[((size_t)(C + k) * NR + h) * SVB + col];
+              }
+              // acc -= t x
+              mp::mac<C>(accR[h], ntr, xr);
+              mp::mac<C>(accR[h], ti, xi);
+              mp::mac<C>(accI[h], ntr, xi);
+              mp::mac<C>(accI[h], nti, xr);
+            }
+          }
+        }
+      }
+    }
+    if (s_expired) break;
+    if (lane < nr) {
       // keep the accumulators non-overlapping between blocks
 #pragma unroll
       for (int h = 0; h < NR; ++h) {
