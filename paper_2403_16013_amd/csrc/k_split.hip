@@ -157,21 +157,17 @@ __device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t
 // registers and issues one MFMA per digit pair p + q <= S - 1 (0-based) into the level
 // accumulator of that pair: all pairs of one level share it.
 //
-// DB (two staging buffers fit in LDS, i.e. DD): the planes of the next chunk are loaded
-// straight into the other buffer (global-to-LDS, one 16-byte piece per lane at the wave's
-// base + 16 x lane) while the current chunk's MFMAs run.  Rows and columns past the edge
-// load the last valid one: they only reach outputs that are never stored.
-template <int S>
-__host__ __device__ constexpr bool split_i8_db() {
-  return 4 * S * 32 * 4 * 16 <= 160 * 1024;
-}
-
+// The planes are loaded straight into LDS (global-to-LDS, one 16-byte piece per lane at
+// the wave's base + 16 x lane).  With one staging buffer per workgroup two workgroups
+// share a CU (for double-double), so one's MFMAs run while the other waits for its planes
+// or flushes its levels; this measured faster than a second buffer per workgroup.  Rows
+// and columns past the edge load the last valid one: they only reach outputs that are
+// never stored.
 template <int C, int S>
 __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   constexpr int W = 7;
-  constexpr bool DB = split_i8_db<S>();
   constexpr int PL = S * 32 * 4;            // 16-byte pieces per operand per chunk
-  extern __shared__ v4i sdig[];             // [DB ? 2 : 1][2][S][32 rows][4 x 16 bytes]
+  extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int64_t tm, tn;
   xcd_tile((g.m + 31) / 32, (g.n + 31) / 32, tm, tn);
@@ -187,110 +183,49 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
 #pragma unroll
     for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
 
-  if constexpr (DB) {
-    // the exponent sums of this lane's four outputs for the three products, fetched up
-    // front so the per-product flush does not wait on memory
-    int tsums[3][4];
+  // the exponent sums of this lane's four outputs for the three products, fetched up
+  // front so the per-product flush does not wait on memory
+  int tsums[3][4];
 #pragma unroll
-    for (int op = 0; op < 3; ++op)
+  for (int op = 0; op < 3; ++op)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
-        tsums[op][e] = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
-                       (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
-      }
-    const int nck = (int)(g.Kpad / 64);
-    const int total = 3 * nck;  // (product, chunk) pairs in order
-    // piece e = (plane p, row r, quarter f) of chunk `it` into buffer `buf`
-    auto issue = [&](int it, int buf) {
-      const int op = it / nck;
-      const int64_t kc = (int64_t)(it % nck) * 64;
-      const int8_t *xo = xs + (int64_t)op * S * g.m * g.Kpad;
-      const int8_t *yo = ys + (int64_t)op * S * g.n * g.Kpad;
-      v4i *dX = sdig + (size_t)buf * 2 * PL, *dY = dX + PL;
-      for (int e0 = w * 64; e0 < PL; e0 += 256) {
-        const int e = e0 + lane;
-        const int f = e & 3, r = (e >> 2) & 31, pl = e >> 7;
-        const int64_t gi = (M0 + r < g.m) ? M0 + r : g.m - 1;
-        const int64_t gj = (N0 + r < g.n) ? N0 + r : g.n - 1;
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(xo + ((int64_t)pl * g.m + gi) * g.Kpad + kc + 16 * f),
-            (__attribute__((address_space(3))) void *)(dX + e0), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(
-            (const void *)(yo + ((int64_t)pl * g.n + gj) * g.Kpad + kc + 16 * f),
-            (__attribute__((address_space(3))) void *)(dY + e0), 16, 0, 0);
-      }
-    };
-    issue(0, 0);
-    for (int op = 0; op < 3; ++op) {
-      double sr, si;
-      op_signs(op, sr, si);
-      v4i acc[S];
-#pragma unroll
-      for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
-      for (int c = 0; c < nck; ++c) {
-        const int it = op * nck + c;
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces of chunk it have landed
-        __syncthreads();                // and everybody else's
-        if (it + 1 < total) issue(it + 1, (it + 1) & 1);
-        const v4i *sX = sdig + (size_t)(it & 1) * 2 * PL, *sY = sX + PL;
-        v4i a[S], b[S];
-#pragma unroll
-        for (int p = 0; p < S; ++p) {
-          a[p] = sX[(p * 32 + frow) * 4 + fk];
-          b[p] = sY[(p * 32 + fcol) * 4 + fk];
-        }
-#pragma unroll
-        for (int p = 0; p < S; ++p)
-#pragma unroll
-          for (int q = 0; q < S - p; ++q)
-            acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
-        __syncthreads();  // this buffer is refilled two chunks later
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int tsum = tsums[0][e];
-#pragma unroll
-        for (int o = 1; o < 3; ++o) tsum = (op == o) ? tsums[o][e] : tsum;
-#pragma unroll
-        for (int top = S - 1; top >= 0; top -= 4) {
-          const int lo = top - 3 < 0 ? 0 : top - 3;
-          double grp = 0.0;
-#pragma unroll
-          for (int l = top; l >= lo; --l)
-            grp = __builtin_fma((double)acc[l][e], ldexp(1.0, (lo - l) * W), grp);
-          grp = ldexp(grp, tsum - (lo + 2) * W);
-          if (sr != 0.0) mp::push<C>(lr[e], 0, sr * grp);
-          mp::push<C>(li[e], 0, si * grp);
-        }
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
+      tsums[op][e] = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
+                     (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
     }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) epilogue<C>(g, m0 + 4 * (lane >> 4) + e, bcol, lr[e], li[e]);
-    return;
-  }
-
-  v4i *sX = sdig, *sY = sdig + PL;
+  const int nck = (int)(g.Kpad / 64);
+  // piece e = (plane p, row r, quarter f) of chunk `it` (product it / nck)
+  auto issue = [&](int it) {
+    const int op = it / nck;
+    const int64_t kc = (int64_t)(it % nck) * 64;
+    const int8_t *xo = xs + (int64_t)op * S * g.m * g.Kpad;
+    const int8_t *yo = ys + (int64_t)op * S * g.n * g.Kpad;
+    v4i *dX = sdig, *dY = sdig + PL;
+    for (int e0 = w * 64; e0 < PL; e0 += 256) {
+      const int e = e0 + lane;
+      const int f = e & 3, r = (e >> 2) & 31, pl = e >> 7;
+      const int64_t gi = (M0 + r < g.m) ? M0 + r : g.m - 1;
+      const int64_t gj = (N0 + r < g.n) ? N0 + r : g.n - 1;
+      __builtin_amdgcn_global_load_lds(
+          (const void *)(xo + ((int64_t)pl * g.m + gi) * g.Kpad + kc + 16 * f),
+          (__attribute__((address_space(3))) void *)(dX + e0), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(
+          (const void *)(yo + ((int64_t)pl * g.n + gj) * g.Kpad + kc + 16 * f),
+          (__attribute__((address_space(3))) void *)(dY + e0), 16, 0, 0);
+    }
+  };
   for (int op = 0; op < 3; ++op) {
     double sr, si;
     op_signs(op, sr, si);
-    const int8_t *xo = xs + (int64_t)op * S * g.m * g.Kpad;
-    const int8_t *yo = ys + (int64_t)op * S * g.n * g.Kpad;
     v4i acc[S];
 #pragma unroll
     for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
-    for (int64_t kc = 0; kc < g.Kpad; kc += 64) {
-      __syncthreads();
-      // stage: entry e = (plane p, row r, quarter f), 16 bytes each
-      for (int e = threadIdx.x; e < S * 32 * 4; e += 256) {
-        const int f = e & 3, r = (e >> 2) & 31, p = e >> 7;
-        const int64_t gi = M0 + r, gj = N0 + r;
-        sX[e] = (gi < g.m) ? *(const v4i *)(xo + ((int64_t)p * g.m + gi) * g.Kpad + kc + 16 * f)
-                           : v4i{0, 0, 0, 0};
-        sY[e] = (gj < g.n) ? *(const v4i *)(yo + ((int64_t)p * g.n + gj) * g.Kpad + kc + 16 * f)
-                           : v4i{0, 0, 0, 0};
-      }
-      __syncthreads();
+    for (int c = 0; c < nck; ++c) {
+      issue(op * nck + c);
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces of the chunk have landed
+      __syncthreads();                // and everybody else's
+      const v4i *sX = sdig, *sY = sdig + PL;
       v4i a[S], b[S];
 #pragma unroll
       for (int p = 0; p < S; ++p) {
@@ -302,14 +237,15 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
 #pragma unroll
         for (int q = 0; q < S - p; ++q)
           acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
+      __syncthreads();  // the buffer is refilled next
     }
     // level l (0-based) carries weight 2^(tau_i + tau_j - (l + 2) W); four consecutive
     // levels span at most 24 + 3 W bits, so their scaled sum is exact in binary64
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
-      const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
-                       (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
+      int tsum = tsums[0][e];
+#pragma unroll
+      for (int o = 1; o < 3; ++o) tsum = (op == o) ? tsums[o][e] : tsum;
 #pragma unroll
       for (int top = S - 1; top >= 0; top -= 4) {
         const int lo = top - 3 < 0 ? 0 : top - 3;
@@ -434,11 +370,11 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
   g.Cm = Cm; g.ci = ci; g.cj = cj; g.alpha = alpha; g.beta = beta;
   const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
   if constexpr (I8) {
-    const size_t lds = sizeof(v4i) * (split_i8_db<S>() ? 4 : 2) * S * 32 * 4;
+    const dim3 grid1((unsigned)(((n + 31) / 32) * ((m + 31) / 32)));
+    const size_t lds = sizeof(v4i) * 2 * S * 32 * 4;
     static LdsAttr attr;
     const hipError_t e = attr.ensure((const void *)k_split_i8<C, S>, (int)lds);
     if (e != hipSuccess) return e;
-    const dim3 grid1((unsigned)(((n + 31) / 32) * ((m + 31) / 32)));
     hipLaunchKernelGGL((k_split_i8<C, S>), grid1, dim3(256), lds, s, g);
   } else {
     hipLaunchKernelGGL((k_split_f64<C, S>), grid, dim3(256), 0, s, g);
