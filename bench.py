@@ -311,8 +311,8 @@ def main():
     if not args.no_variants:
         var = {}
         runs = ((2, "4m", panel, 2), (2, "3m", 128, 2), (2, "split_i8", 128, 2),
-                (2, "split_f64", 128, 1), (3, "3m", panel, 1), (3, "split_i8", 128, 1),
-                (4, "3m", panel, 1), (4, "split_i8", 128, 1))
+                (2, "split_i8", panel, 2), (2, "split_f64", 128, 1), (3, "3m", panel, 1),
+                (3, "split_i8", panel, 1), (4, "3m", panel, 1), (4, "split_i8", panel, 1))
         probs = {2: (A0, B0)}
         for (C, meth, pnl, steps) in runs:
             if C not in probs:

@@ -92,14 +92,19 @@ PanelGeom panel_geometry(int C, int64_t mp, int kb) {
   while (rmax > 1 && panel_lds(C, kb, rmax) > PLDS_BUDGET) --rmax;
   // aim for about 96 workgroups: fewer makes the per-column barrier cheaper, more
   // spreads the rank-1 work; never below 8 rows each
-  // (MPLU_PANEL_WGS overrides the target, for tuning)
+  // (MPLU_PANEL_WGS and MPLU_PANEL_RMIN override the target and the row floor, for tuning)
   static const int target = [] {
     const char *e = getenv("MPLU_PANEL_WGS");
     const int t = e ? atoi(e) : 96;
     return t < 1 ? 96 : t;
   }();
+  static const int rmin = [] {
+    const char *e = getenv("MPLU_PANEL_RMIN");
+    const int t = e ? atoi(e) : 8;
+    return t < 1 ? 8 : t;
+  }();
   int64_t R = (mp + target - 1) / target;
-  if (R < 8) R = 8;
+  if (R < rmin) R = rmin;
   if (R > rmax) R = rmax;
   int64_t G = (mp + R - 1) / R;
   if (G > PGMAX || G > device_cus()) return g;
@@ -168,6 +173,34 @@ __device__ __forceinline__ void dpp_step(double (&v)[C], int &idx) {
 // lane, and every wave reducing the same candidates, ends with the same winner.
 template <int C>
 __device__ __forceinline__ void wave_argmax(double (&v)[C], int &idx) {
+  // Common case first: the largest leading component, by a plain maximum over doubles.
+  // When a single lane holds it, that lane's candidate beats every other in the full
+  // order, so it is the winner.  Ties on the leading component, and waves whose present
+  // candidates are all NaN (the maximum ignores them, and one of them must still win over
+  // the missing ones), take the full reduction below; the branches are uniform.
+  {
+    if (__ballot(idx != INT_MAX) == 0ull) {  // no candidate in the whole wave
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = 0.0;
+      return;
+    }
+    const double h = (idx == INT_MAX) ? -1.0 : v[0];  // a missing candidate loses
+    double m = h;
+    m = fmax(m, dpp_d<0x128>(m));
+    m = fmax(m, dpp_d<0x124>(m));
+    m = fmax(m, dpp_d<0x122>(m));
+    m = fmax(m, dpp_d<0x121>(m));
+    const double mx = fmax(fmax(lane_value(m, 0), lane_value(m, 16)),
+                           fmax(lane_value(m, 32), lane_value(m, 48)));
+    const unsigned long long hit = __ballot(h == mx);
+    if (mx >= 0.0 && __popcll(hit) == 1) {
+      const int s = __ffsll((long long)hit) - 1;
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = lane_value(v[c], s);
+      idx = __builtin_amdgcn_readlane(idx, s);
+      return;
+    }
+  }
   dpp_step<C, 0x128>(v, idx);  // row_ror:8
   dpp_step<C, 0x124>(v, idx);  // row_ror:4
   dpp_step<C, 0x122>(v, idx);  // row_ror:2
@@ -390,6 +423,9 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
         }
       }
       wave_argmax<C>(bv, bi);
+      // a winner is always a row >= k of this panel; only records left behind by an
+      // expired wait could say otherwise, and they must not steer any address
+      if (bi < k || (int64_t)bi >= mp) bi = k;
       const int gp = bi / R;
       {
         // the record of workgroup gp sits in lane gp % 64, slot gp / 64 (gp is uniform)

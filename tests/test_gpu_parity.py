@@ -213,6 +213,51 @@ def test_zero_column_sets_info(mp, orc, C):
     assert list(ipiv.cpu().numpy()) == list(range(1, 41))
 
 
+@pytest.mark.parametrize("C", [2, 4])
+@pytest.mark.parametrize("rows", [(3, 1), (150, 5), (7, 180)])
+def test_pivot_tie_on_leading_component(mp, orc, C, rows):
+    """Two candidates whose cabs1 agree in the leading component and differ below it:
+    the larger full value wins whatever the row order, in one wave (3 vs 1) or across
+    workgroups (150 vs 5, 7 vs 180)."""
+    n = 200
+    A = orc.canon(synthgen.uniform(n, n, C, 75))
+    A[:, :, 0, :] *= 0.25  # column 0 otherwise below 0.5 in cabs1
+    win, lose = rows
+    A[:, :, 0, win] = 0.0
+    A[:, :, 0, lose] = 0.0
+    A[0, 0, 0, win] = 1.0
+    A[0, 1, 0, win] = 2.0 ** -60
+    A[0, 0, 0, lose] = 1.0
+    A[0, 1, 0, lose] = -(2.0 ** -60)
+    _, piv_o, _ = orc.getf2(A[:, :, :1, :].copy())
+    assert int(piv_o[0]) == win + 1
+    for method in ("3m", "split_i8"):
+        T = to_dev(A)
+        ipiv, info = mp.getrf(T, panel=64, method=method)
+        sync()
+        assert int(ipiv[0].item()) == win + 1
+
+
+@pytest.mark.parametrize("C", [2, 4])
+def test_nan_entries_finish_with_valid_pivots(mp, C):
+    """NaN entries do not stop the factorisation or the solves: every pivot index stays
+    within the rows still to be eliminated (ipiv[i] in [i + 1, n])."""
+    n = 300
+    A = synthgen.uniform(n, n, C, 76)
+    A[0, 0, 5, 17] = np.nan       # one entry
+    A[:, :, 130, :] = np.nan      # a whole column
+    A[1, 0, 200, 40:90] = np.nan  # part of a column, imaginary parts
+    for method in ("3m", "split_i8"):
+        T = to_dev(A)
+        ipiv, info = mp.getrf(T, panel=64, method=method)
+        sync()
+        piv = ipiv.cpu().numpy()
+        assert np.all(piv >= np.arange(1, n + 1)) and np.all(piv <= n)
+        B = to_dev(synthgen.uniform(n, 2, C, 77))
+        mp.getrs(T, ipiv, B)
+        sync()
+
+
 def test_empty_and_tiny(mp, orc):
     import torch
 
