@@ -29,13 +29,15 @@ static constexpr int32_t MPLU_SYNC_TIMEOUT = -9999;  // mirrors MPLU_INFO_SYNC_T
 
 // ------------------------------------------------------------------ workspace layout
 // [0, 256)              barrier words: count, generation, timeout flag
-// part  : 2 x PGMAX x (3C+1) doubles  (cabs1 components, row index, the complex pivot)
+// part  : 2 x (C+1) x PGMAX doubles  (cabs1 components, row index; field-major: field f
+//         of workgroup g at f * PGMAX + g)
+// rcp   : 2 x 2C x PGMAX doubles  (reciprocal of each candidate pivot, same layout)
 // cand  : 2 x PGMAX x 2C x kb doubles
 // rowk  : 2 x 2C x kb doubles
 // swl   : 1 + 2 x (2 kb) int32  (count, dst rows, src rows)
 struct PanelWS {
   unsigned *bar;
-  double *part, *cand, *rowk;
+  double *part, *rcp, *cand, *rowk;
   int32_t *swl;
 };
 
@@ -47,7 +49,9 @@ static inline PanelWS carve(void *ws, int C, int kb, size_t *total) {
   PanelWS w;
   w.bar = (unsigned *)b;
   w.part = (double *)(b + off);
-  off = align256(off + sizeof(double) * 2 * PGMAX * (3 * C + 1));
+  off = align256(off + sizeof(double) * 2 * PGMAX * (C + 1));
+  w.rcp = (double *)(b + off);
+  off = align256(off + sizeof(double) * 2 * PGMAX * 2 * C);
   w.cand = (double *)(b + off);
   off = align256(off + sizeof(double) * 2 * PGMAX * 2 * C * kb);
   w.rowk = (double *)(b + off);
@@ -269,6 +273,14 @@ __device__ __forceinline__ void grid_wait(unsigned *bar, unsigned want) {
   __syncthreads();
 }
 
+// A reciprocal slot holds this signalling NaN from the moment its column's barrier is
+// entered until the reciprocal is stored.  Arithmetic only ever produces quiet NaNs, so
+// a stored reciprocal never has this bit pattern.
+static constexpr long long RCP_PENDING = 0x7FF4A5A5A5A5A5A5ll;
+__device__ __forceinline__ bool rcp_pending(double v) {
+  return __double_as_longlong(v) == RCP_PENDING;
+}
+
 // element (row lr, column c, plane q) of this workgroup's rows in LDS
 #define SA(c, q, lr) sA[((size_t)(c) * Q + (q)) * R + (lr)]
 
@@ -284,7 +296,7 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   // update its waves should win instruction issue
   __builtin_amdgcn_s_setprio(3);
   constexpr int Q = 2 * C;
-  constexpr int PREC = 3 * C + 1;  // candidate record: cabs1, row, complex value
+  constexpr int PREC = C + 1;  // candidate record: cabs1, row
   const int kb = a.kb, R = a.R, G = a.G;
   const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t mp = a.m - a.j;
@@ -313,6 +325,7 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   for (int k = 0; k < kb; ++k) {
     const int par = k & 1;
     double *part = a.w.part + (size_t)par * PGMAX * PREC;
+    double *rcpw = a.w.rcp + (size_t)par * PGMAX * Q;
     double *cand = a.w.cand + (size_t)par * PGMAX * Q * kb;
     double *rowk = a.w.rowk + (size_t)par * Q * kb;
 
@@ -341,14 +354,15 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     wave_argmax<C>(v, idx);
 
     // (2) publish the candidate (value, row, row contents) and, if owned, row k
+    // (records are stored field by field across workgroups, part[field][g], so that one
+    // load instruction of the reader covers 64 workgroups' field in four cache lines)
     if (t == 0) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) put(&part[g * PREC + c], v[c]);
-      put(&part[g * PREC + C], (idx == INT_MAX) ? -1.0 : (double)idx);
-      if (idx != INT_MAX) {
+      for (int c = 0; c < C; ++c) put(&part[c * PGMAX + g], v[c]);
+      put(&part[C * PGMAX + g], (idx == INT_MAX) ? -1.0 : (double)idx);
+      // this slot was last read before the previous column's barrier completed
 #pragma unroll
-        for (int q = 0; q < Q; ++q) put(&part[g * PREC + C + 1 + q], SA(k, q, (int)(idx - r0)));
-      }
+      for (int q = 0; q < Q; ++q) put(&rcpw[q * PGMAX + g], __longlong_as_double(RCP_PENDING));
     }
     if (idx != INT_MAX) {
       const int lr = (int)(idx - r0);
@@ -366,12 +380,31 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     }
     grid_arrive(a.w.bar);
 
-    // (3) while the barrier is in flight: the pending step k-1 update of columns > k
-    if (!prev_zero && k + 1 < kb) {
+    // (3) while the barrier is in flight: wave 1 inverts this workgroup's candidate pivot
+    // (only the winner's reciprocal will be read, by every workgroup, with the pivot
+    // row); the other three waves apply the pending step k-1 update of columns > k
+    if (w == 1) {
+      if (lane == 0 && idx != INT_MAX) {
+        double pr[C], pi[C], rr[C], ri[C];
+        const int lr = (int)(idx - r0);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          pr[c] = SA(k, c, lr);
+          pi[c] = SA(k, C + c, lr);
+        }
+        mp::zrecip<C>(pr, pi, rr, ri);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          put(&rcpw[c * PGMAX + g], rr[c]);
+          put(&rcpw[(C + c) * PGMAX + g], ri[c]);
+        }
+      }
+    } else if (!prev_zero && k + 1 < kb) {
       const int lo = (int)(k - r0 > 0 ? k - r0 : 0);  // rows with local index >= k
       const int cnt = nr - lo;
       const int ncol = kb - k - 1;
-      for (int e = t; e < cnt * ncol; e += PNT) {
+      const int pt = (w == 0) ? t : t - 64;  // thread index among waves 0, 2 and 3
+      for (int e = pt; e < cnt * ncol; e += PNT - 64) {
         const int r = lo + e % cnt;
         const int c = k + 1 + e / cnt;
         double xr[C], xi[C], lr_[C], li[C], ur[C], ui[C];
@@ -403,16 +436,19 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
       int bi = INT_MAX;
 #pragma unroll
       for (int c = 0; c < C; ++c) bv[c] = 0.0;
-      double pz[PGMAX / 64][Q], pc[PGMAX / 64][C], px[PGMAX / 64];
+      double pc[PGMAX / 64][C], px[PGMAX / 64];
 #pragma unroll
       for (int it = 0; it < PGMAX / 64; ++it) {
         const int gg = lane + 64 * it;
         const bool have = gg < G;
 #pragma unroll
-        for (int c = 0; c < C; ++c) pc[it][c] = have ? get(&part[gg * PREC + c]) : 0.0;
-        px[it] = have ? get(&part[gg * PREC + C]) : -1.0;
+        for (int c = 0; c < C; ++c) pc[it][c] = 0.0;
+        px[it] = -1.0;
+        if (64 * it < G) {  // uniform: slots of absent workgroups are never loaded
 #pragma unroll
-        for (int q = 0; q < Q; ++q) pz[it][q] = have ? get(&part[gg * PREC + C + 1 + q]) : 0.0;
+          for (int c = 0; c < C; ++c) pc[it][c] = have ? get(&part[c * PGMAX + gg]) : 0.0;
+          px[it] = have ? get(&part[C * PGMAX + gg]) : -1.0;
+        }
       }
 #pragma unroll
       for (int it = 0; it < PGMAX / 64; ++it) {
@@ -426,19 +462,6 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
       // a winner is always a row >= k of this panel; only records left behind by an
       // expired wait could say otherwise, and they must not steer any address
       if (bi < k || (int64_t)bi >= mp) bi = k;
-      const int gp = bi / R;
-      {
-        // the record of workgroup gp sits in lane gp % 64, slot gp / 64 (gp is uniform)
-        const int gl = gp & 63, git = gp >> 6;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          double sel = pz[0][q];
-#pragma unroll
-          for (int it = 1; it < PGMAX / 64; ++it) sel = (git == it) ? pz[it][q] : sel;
-          const double val = lane_value(sel, gl);
-          if (lane == 0) sRcp[q] = val;  // the pivot itself for now
-        }
-      }
       if (lane == 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c) sRedV[c] = bv[c];
@@ -451,10 +474,13 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     for (int c = 0; c < C; ++c) bv[c] = sRedV[c];
     const int p = sRedI[0];
     {
-      // every thread fetches its share of the two rows while wave 1 inverts the pivot
+      // every thread fetches its share of the two rows; lanes of wave 1 fetch the
+      // winner's reciprocal in the same round trip and wait for it if it is still pending
       const int gp = p / R;
       constexpr int NE = (2 * 4 * PKBMAX + PNT - 1) / PNT;
       double rowv[NE], rowk_v[NE];
+      const bool rl = (w == 1) && (lane < Q);
+      double rv = rl ? get(&rcpw[lane * PGMAX + gp]) : 0.0;
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
         const int e = t + i * PNT;
@@ -463,19 +489,21 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
           rowk_v[i] = get(&rowk[e]);
         }
       }
-      if (t == 64) {
-        double pr[C], pi[C], rr[C], ri[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          pr[c] = sRcp[c];
-          pi[c] = sRcp[C + c];
+      if (w == 1) {
+        unsigned spins = 0;
+        while (__ballot(rl && rcp_pending(rv)) != 0ull) {
+          // bounded like the grid barrier, and given up at once after an expiry
+          if ((spins & 255u) == 0u &&
+              __hip_atomic_load(&a.w.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            break;
+          if (++spins > SPIN_LIMIT) {
+            if (lane == 0) __hip_atomic_store(&a.w.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          if (rl && rcp_pending(rv)) rv = get(&rcpw[lane * PGMAX + gp]);
         }
-        mp::zrecip<C>(pr, pi, rr, ri);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          sRcp[c] = rr[c];
-          sRcp[C + c] = ri[c];
-        }
+        if (rl) sRcp[lane] = rv;
       }
 #pragma unroll
       for (int i = 0; i < NE; ++i) {
