@@ -11,7 +11,9 @@ value = 8 n^3 / 3 / t_step (the LAPACK zgetrf operation count; the solve is insi
 step but not counted).  Besides the headline line, the JSON carries: the backward error
 of the last solve (exact-enough residual computed on the GPU in quadruple-double), the
 4M / triple-double / quadruple-double variants, the roofline of the dominant kernel (the
-3M trailing-update GEMM, timed live with HIP events) and the CPU oracle baseline.
+3M trailing-update GEMM, timed live with HIP events), the complex matrix-product
+benchmark of Sec. 2.4 (C := A B, n = 2048, every product form) and the CPU oracle baseline.
+`--panel-sweep 32,64,96,128` instead runs the panel-width sweep on the paper's LU workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096] [--panel 64]
 """
@@ -49,6 +51,12 @@ def parse():
     p.add_argument("--no-roofline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target length of the CPU oracle sample")
+    p.add_argument("--no-matmul", action="store_true")
+    p.add_argument("--matmul-n", type=int, default=2048,
+                   help="size of the square complex matrix-product benchmark (Sec. 2.4)")
+    p.add_argument("--panel-sweep", default="",
+                   help="comma-separated panel widths: instead of the headline, run the "
+                        "panel-width sweep on the paper's LU workload at --n and print it")
     p.add_argument("--calib-copy", action="store_true",
                    help="first run one plain 1 GiB device-to-device copy (a reference for "
                         "hardware memory counters)")
@@ -218,6 +226,90 @@ def split_roofline(mp, torch, A0, panel, n_launch=12):
             "panel": panel}
 
 
+def mp_diff(torch, X4, R4):
+    """Leading-order value of X - R for two quadruple-double plane tensors, as complex128
+    (component differences summed in binary64; both agree to far more than 53 bits, so
+    this carries the difference to a few digits)."""
+    d = (X4 - R4).sum(dim=1)
+    return torch.complex(d[0], d[1])
+
+
+def hi_abs(torch, T):
+    """cabs1 of the leading components, as a (rows, cols) float64 matrix."""
+    return (T[0, 0].abs() + T[1, 0].abs()).transpose(0, 1)
+
+
+def matmul_bench(mp, torch, synthgen, n, reps=3):
+    """The complex matrix-product benchmark of Sec. 2.4: C := A B with square n x n
+    operands whose leading components are uniform on [0, 1], for DD / TD / QD and each
+    product form (4M, 3M, split INT8, split FP64).  Each product is timed with HIP events
+    on the stream (one warm-up, then the mean of `reps`).  Error: max over elements of
+    |C - C_ref| / (|A| |B|)_ij, C_ref the quadruple-double 4M product of the same
+    (exactly widened) operands; for QD this is the difference from QD 4M itself."""
+    out = {}
+    for C in (2, 3, 4):
+        A = torch.from_numpy(synthgen.uniform(n, n, C, 11, lo=0.0, hi=1.0)).cuda()
+        B = torch.from_numpy(synthgen.uniform(n, n, C, 12, lo=0.0, hi=1.0)).cuda()
+        mp.renorm_(A)
+        mp.renorm_(B)
+        ref = mp.gemm(mp.convert(A, 4), mp.convert(B, 4), None, method="4m")
+        scale = hi_abs(torch, A) @ hi_abs(torch, B)
+        for meth in ("4m", "3m", "split_i8", "split_f64"):
+            times = []
+            for r in range(reps + 1):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                Cm = mp.gemm(A, B, None, method=meth)
+                e1.record()
+                torch.cuda.synchronize()
+                if r:
+                    times.append(e0.elapsed_time(e1))
+            d = mp_diff(torch, mp.convert(Cm, 4), ref).transpose(0, 1)
+            err = (d.real.abs() + d.imag.abs()).div(scale).max().item()
+            ms = sum(times) / len(times)
+            key = f"{['', '', 'DD', 'TD', 'QD'][C]}_{meth}"
+            out[key] = {"ms": round(ms, 3), "gflops": round(8.0 * n ** 3 / (ms / 1e3) / 1e9, 2),
+                        "err": err}
+            print(f"[bench] matmul n={n} {key}: {out[key]}", file=sys.stderr, flush=True)
+            del Cm
+        del A, B, ref, scale
+        torch.cuda.empty_cache()
+    return {"n": n, "op": "C := A B, complex, leading components uniform[0,1]",
+            "flops": "8 n^3 per product", "results": out}
+
+
+def panel_sweep(mp, torch, synthgen, n, panels, steps=2):
+    """Panel width (the paper's block size K) sweep on the paper's LU workload of Sec. 4:
+    leading components uniform on [0, 1], x_k = k + k i, b = A x formed in quadruple-double
+    and rounded to the working format (exact to 2^-209 relative for DD and TD; for QD the
+    rounding of b is itself of the order of the working precision).  Reports gesv time,
+    the normwise backward error and the maximum relative error max_k |x_k - x*_k| / |x*_k|."""
+    out = []
+    for C in (2, 3, 4):
+        A0 = torch.from_numpy(synthgen.uniform(n, n, C, 0, lo=0.0, hi=1.0)).cuda()
+        mp.renorm_(A0)
+        xt4 = torch.from_numpy(synthgen.k_plus_ki(n, 4)).cuda()
+        b4 = mp.gemm(mp.convert(A0, 4), xt4, None, method="4m")
+        B0 = mp.convert(b4, C)
+        xmod = hi_abs(torch, xt4)[:, 0] / 2 ** 0.5   # |k + k i| = sqrt(2) k
+        for meth in ("4m", "3m", "split_i8", "split_f64"):
+            for K in panels:
+                ms, _, X, info = time_gesv(mp, torch, A0, B0, steps, 1, K, meth)
+                eta = backward_error(mp, torch, A0, X, B0)
+                d = mp_diff(torch, mp.convert(X, 4), xt4).transpose(0, 1)[:, 0]
+                rel = (d.abs() / xmod).max().item()
+                rec = {"prec": ["", "", "DD", "TD", "QD"][C], "method": meth, "panel": K,
+                       "ms": round(ms, 3), "gflops": round(eff_gflops(n, ms / 1e3), 2),
+                       "eta": eta, "max_rel_err": rel, "info": info}
+                print(f"[sweep] {rec}", file=sys.stderr, flush=True)
+                out.append(rec)
+                del X
+        del A0, B0, b4, xt4
+        torch.cuda.empty_cache()
+    return out
+
+
 def committed_traffic(kernel_src):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, or None when that kernel's source changed after the counters were taken."""
@@ -268,6 +360,12 @@ def main():
     import synthgen
 
     n, panel, method = args.n, args.panel, args.method
+    if args.panel_sweep:
+        panels = [int(k) for k in args.panel_sweep.split(",")]
+        res = panel_sweep(mp, torch, synthgen, n, panels)
+        print(json.dumps({"panel_sweep": {"n": n, "workload": "the paper's LU workload: "
+                          "A uniform[0,1] complex, x_k = k + k i", "results": res}}))
+        return
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         dst = torch.empty_like(src)
@@ -329,6 +427,8 @@ def main():
             torch.cuda.empty_cache()
         del probs
         line["variants"] = var
+    if not args.no_matmul:
+        line["matmul"] = matmul_bench(mp, torch, synthgen, args.matmul_n)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(synthgen, n, args.cpu_seconds)

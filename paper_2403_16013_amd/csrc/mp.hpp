@@ -11,8 +11,8 @@
 // o < C-1 goes through TwoSum and its rounding error is pushed into level o+1; the last
 // level is a plain sum.  Accumulating sums of products this way keeps every level
 // exact except the last, so a K-term dot product has an error of order K u |a||b| with
-// u = 2^(-53 C); the value is renormalised to non-overlapping components only when it
-// is stored (this is the accumulation scheme of Ogita, Rump and Oishi's Dot2 applied per
+// u = 2^(-53 C) as long as the levels are re-levelled (tidy) every few pushes in long
+// sums; the value is renormalised to non-overlapping components only when it is stored (this is the accumulation scheme of Ogita, Rump and Oishi's Dot2 applied per
 // level).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -102,6 +102,24 @@ __host__ __device__ __forceinline__ void mac_scalar(double (&l)[C], const double
     push<C>(l, i + 1, e);
   }
   l[C - 1] = __builtin_fma(a[C - 1], s, l[C - 1]);
+}
+
+// Re-level an accumulator in place, exactly: one bottom-up chain of TwoSum leaves the
+// value unchanged and each level again about the rounding error of the level above.
+// Long accumulations call it every few pushes.  Without it, when the leading level keeps
+// growing (a sum of same-sign terms), every push hands the next level an error of half an
+// ulp of the grown leading level; those errors pile up, and for C >= 3 the plain last
+// level then rounds relative to the piled-up size, so an n-term sum loses accuracy faster
+// than n u.
+template <int C>
+__host__ __device__ __forceinline__ void tidy(double (&l)[C]) {
+#pragma unroll
+  for (int k = C - 1; k > 0; --k) {
+    double s, e;
+    two_sum(l[k - 1], l[k], s, e);
+    l[k - 1] = s;
+    l[k] = e;
+  }
 }
 
 // Renormalise a level accumulator into non-overlapping components.  Each pass is a

@@ -58,6 +58,31 @@ void mph_zrecip(int C, const double *a, double *o) {
     cp_out<K>(orr, o); cp_out<K>(oi, o + C);
   })
 }
+// sum_i a_i b_i with the accumulator re-levelled (mp::tidy) after every `period` terms
+void mph_dot_tidy(int C, int n, int period, const double *a, const double *b, double *o) {
+  DISPATCH(C, {
+    double l[K];
+    mp::set_zero<K>(l);
+    for (int i = 0; i < n; ++i) {
+      double x[K], y[K];
+      cp_in<K>(a + i * C, x); cp_in<K>(b + i * C, y);
+      mp::mac<K>(l, x, y);
+      if (period > 0 && (i + 1) % period == 0) mp::tidy<K>(l);
+    }
+    double z[K];
+    mp::renorm<K>(l, z);
+    cp_out<K>(z, o);
+  })
+}
+// the raw levels of mp::tidy applied to a C-level accumulator given as l[C]
+void mph_tidy(int C, const double *l, double *o) {
+  DISPATCH(C, {
+    double v[K];
+    cp_in<K>(l, v);
+    mp::tidy<K>(v);
+    cp_out<K>(v, o);
+  })
+}
 // sum_i a_i b_i of n real values (row-major n x C) in one level accumulator
 void mph_dot(int C, int n, const double *a, const double *b, double *o) {
   DISPATCH(C, {

@@ -287,3 +287,40 @@ def test_metric_eta_n4096(mp, orc, C):
         eta = orc.backward_error(A, x, b)
         record("metric", C=C, panel=panel, eta=eta, seconds=dt)
         assert eta <= 10 * n * U_FMT[C]
+
+
+@pytest.mark.parametrize("C", [2, 3, 4])
+def test_matmul_paper_workload_n2048_sampled(mp, orc, C):
+    """The matrix-product benchmark of Sec. 2.4 at the size the benchmark times (n = 2048,
+    leading components uniform on [0, 1]) in every product form: a 24 x 24 block of
+    sampled rows and columns of each GPU product against the oracle's product of the same
+    rows and columns, elementwise within 4 (n + 4) u sum |a||b| (plus the slicing term of
+    the split forms, 2^-(53C+2) below each row / column maximum)."""
+    import torch
+
+    n = 2048
+    A = orc.canon(synthgen.uniform(n, n, C, 11, lo=0.0, hi=1.0))
+    B = orc.canon(synthgen.uniform(n, n, C, 12, lo=0.0, hi=1.0))
+    rng = np.random.default_rng(3)
+    rows = np.sort(rng.choice(n, 24, replace=False))
+    cols = np.sort(rng.choice(n, 24, replace=False))
+    As = np.ascontiguousarray(A[:, :, :, rows])
+    Bs = np.ascontiguousarray(B[:, :, cols, :])
+    a = (np.abs(As[0, 0]) + np.abs(As[1, 0])).T
+    b = (np.abs(Bs[0, 0]) + np.abs(Bs[1, 0])).T
+    S = a @ b
+    slicing = 16 * n * 2.0 ** (-53 * C - 2) * np.outer(
+        (np.abs(A[0, 0]) + np.abs(A[1, 0])).T.max(axis=1)[rows],
+        (np.abs(B[0, 0]) + np.abs(B[1, 0])).T.max(axis=0)[cols])
+    Ad, Bd = to_dev(A), to_dev(B)
+    worst = {}
+    for method in ("4m", "3m", "split_i8", "split_f64"):
+        ref = orc.gemm(As, Bs, None, method=4 if method == "4m" else 3, threads=0)
+        got = to_host(mp.gemm(Ad, Bd, None, method=method))[:, :, cols][:, :, :, rows]
+        d = orc.diff(np.ascontiguousarray(got), ref)
+        tol = 4 * (n + 4) * U_FMT[C] * S + (slicing if method.startswith("split") else 0)
+        assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol), method
+        worst[method] = float(np.max(np.abs(d) / S))
+    record("matmul_n2048", C=C, err_over_sum_abs=worst)
+    del Ad, Bd
+    torch.cuda.empty_cache()

@@ -461,3 +461,18 @@ def test_lookahead_two_streams_concurrently(mp, orc):
     for (R, rp), T, ip in zip(ref, (T1, T2), (ip1, ip2)):
         assert np.array_equal(ip.cpu().numpy(), rp)
         assert np.array_equal(to_host(T), R)
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["4m", "3m"] + SPLIT)
+def test_matmul_uniform01_square_vs_oracle(mp, orc, C, method):
+    """The matrix product of Sec. 2.4 (C := A B, square, leading components uniform on
+    [0, 1]) in every product form, at a size with several K blocks and ragged tiles."""
+    n = 150
+    A = orc.canon(synthgen.uniform(n, n, C, 30, lo=0.0, hi=1.0))
+    B = orc.canon(synthgen.uniform(n, n, C, 31, lo=0.0, hi=1.0))
+    ref = orc.gemm(A, B, None, method=4 if method == "4m" else 3)
+    got = to_host(mp.gemm(to_dev(A), to_dev(B), None, method=method))
+    d = orc.diff(got, ref)
+    tol = (split_tol if method in SPLIT else gemm_tol)(A, B, None, "N", "N", C, n)
+    assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)

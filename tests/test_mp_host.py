@@ -139,3 +139,48 @@ def test_dot_accuracy(H, C):
         ex = sum((fr(x) * fr(y) for x, y in zip(a, b)), Fraction(0))
         S = sum((abs(fr(x) * fr(y)) for x, y in zip(a, b)), Fraction(0))
         assert abs(fr(list(o)) - ex) <= 4 * (n + 2) * u * S
+
+
+@pytest.mark.parametrize("C", CS)
+def test_tidy_is_exact(H, C):
+    """Re-levelling leaves the value of an accumulator unchanged, bit for bit in sum."""
+    rng = np.random.default_rng(40 + C)
+    for _ in range(500):
+        e = int(rng.integers(-20, 20))
+        lv = [float(np.ldexp(rng.uniform(-1, 1), e - int(rng.integers(0, 40)) * k))
+              for k in range(C)]
+        o = arr([0] * C)
+        H.mph_tidy(C, arr(lv), o)
+        assert fr(list(o)) == fr(lv)
+
+
+@pytest.mark.parametrize("C", CS)
+def test_long_same_sign_dot_with_tidy(H, C):
+    """A long sum of same-sign products (the paper's uniform [0, 1] matrix-product
+    workload, n = 2048) stays within 4 (n + 2) u sum |a_i b_i| when the accumulator is
+    re-levelled every 16 terms, as the long products of the library do."""
+    rng = np.random.default_rng(50 + C)
+    u = Fraction(2) ** (-53 * C)
+    n = 2048
+
+    def vec():
+        out = []
+        for _ in range(n):
+            x = Fraction(float(rng.uniform(0, 1)))
+            t = float(x)
+            for k in range(1, C):
+                t = t * 2.0 ** -53 * float(rng.uniform(-1, 1))
+                x += Fraction(t)
+            comps = []
+            for k in range(C):
+                f = float(x)
+                comps.append(f)
+                x -= Fraction(f)
+            out.append(comps)
+        return out
+
+    a, b = vec(), vec()
+    ex = sum((fr(x) * fr(y) for x, y in zip(a, b)), Fraction(0))
+    o = arr([0] * C)
+    H.mph_dot_tidy(C, n, 16, arr(sum(a, [])), arr(sum(b, [])), o)
+    assert abs(fr(list(o)) - ex) <= 4 * (n + 2) * u * ex
