@@ -12,7 +12,8 @@ step but not counted).  Besides the headline line, the JSON carries: the backwar
 of the last solve (exact-enough residual computed on the GPU in quadruple-double), the
 4M / triple-double / quadruple-double variants, the roofline of the dominant kernel (the
 3M trailing-update GEMM, timed live with HIP events), the complex matrix-product
-benchmark of Sec. 2.4 (C := A B, n = 2048, every product form) and the CPU oracle baseline.
+benchmark of Sec. 2.4 (C := A B, n = 2048, every product form), the real (Im = 0) gesv
+and the CPU oracle baseline.
 `--panel-sweep 32,64,96,128` instead runs the panel-width sweep on the paper's LU workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096] [--panel 64]
@@ -310,6 +311,44 @@ def panel_sweep(mp, torch, synthgen, n, panels, steps=2):
     return out
 
 
+def real_bench(mp, torch, synthgen, n, panel, steps=2):
+    """Real DD / QD gesv (the Im = 0 case, mplu_dgesv) on the real part of the headline
+    matrix, b = A 1; effective GFLOPS from the real LU count 2 n^3 / 3; eta from the QD
+    residual of the complex embedding."""
+    out = {}
+    for C in (2, 4):
+        Z, _ = make_problem(mp, torch, synthgen, n, C)
+        A0 = Z[0].clone()
+        del Z
+        X1 = torch.from_numpy(synthgen.ones(n, 1, C)[0]).cuda()
+        B0 = mp.dgemm(A0, X1)
+        nb = ct.c_size_t()
+        o = mp._opts(panel, "3m")
+        mp.lib().mplu_dgesv_wsbytes(C, n, 1, ct.byref(o), ct.byref(nb))
+        work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        As = [A0.clone() for _ in range(steps + 1)]
+        Bs = [B0.clone() for _ in range(steps + 1)]
+        mp.dgesv(As[0], Bs[0], panel=panel, work=work)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        infos = [mp.dgesv(As[s], Bs[s], panel=panel, work=work)[1] for s in range(1, steps + 1)]
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        emb = lambda R: torch.stack([R, torch.zeros_like(R)])
+        eta = backward_error(mp, torch, emb(A0), emb(Bs[-1]), emb(B0))
+        key = ["", "", "DD", "TD", "QD"][C]
+        out[key] = {"ms": round(ms, 3), "gflops": round(2.0 * n ** 3 / 3.0 / (ms / 1e3) / 1e9, 2),
+                    "eta": eta, "info": max(int(i.item()) for i in infos)}
+        print(f"[bench] real {key}: {out[key]}", file=sys.stderr, flush=True)
+        del As, Bs, A0, B0, work
+        torch.cuda.empty_cache()
+    return {"n": n, "panel": panel, "op": "real gesv (mplu_dgesv), 1 RHS",
+            "flops": "2 n^3 / 3 per factorisation", "results": out}
+
+
 def committed_traffic(kernel_src):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, or None when that kernel's source changed after the counters were taken."""
@@ -429,6 +468,8 @@ def main():
         line["variants"] = var
     if not args.no_matmul:
         line["matmul"] = matmul_bench(mp, torch, synthgen, args.matmul_n)
+    if not args.no_variants:
+        line["real"] = real_bench(mp, torch, synthgen, n, panel)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(synthgen, n, args.cpu_seconds)

@@ -166,6 +166,68 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k,
                int method, const mplu_opts_t *opts, void *d_work, size_t work_bytes,
                void *stream);
 
+/*
+ * REAL MATRICES -- the Im = 0 case of the same method (the paper's earlier real DD / TD /
+ * QD LU that Sec. 1 builds on; Sec. 3 with every imaginary part zero).
+ *
+ * A real multi-component matrix is C planes: plane c (component c) at
+ * planes + c*plane_stride, each column-major (element (i, j) at [j*ld + i]).
+ *
+ * mplu_dgetrf / mplu_dgetrs / mplu_dgesv take a complex copy of their operands in the
+ * workspace (imaginary planes zero) and run the complex panels, interchanges and
+ * triangular solves on it, with the trailing updates done by the real product (only
+ * T1 = Re(L21) Re(U12) of Eq. 3m_cemm, real planes only); the results are copied back.
+ * Factors, pivots and solutions are bitwise those of the complex routines with the 3M
+ * update on the same matrix with zero imaginary parts.  opts->gemm must be MPLU_GEMM_4M
+ * or MPLU_GEMM_3M (both select the real product); the split methods return
+ * MPLU_E_UNSUPPORTED.  Argument meaning, pivots, d_info, ownership and errors are as for
+ * the complex routines; the pivot measure is |a| in full precision.
+ */
+typedef struct {
+  double *planes;
+  int64_t ld;           /* >= max(1, rows)                                   */
+  int64_t plane_stride; /* >= ld * cols; distance between planes in doubles  */
+} mplu_dmat_t;
+
+/* mplu_dgetrf_wsbytes -- workspace bytes mplu_dgetrf needs (a complex m x n copy plus
+ * the complex factorisation's workspace). */
+int mplu_dgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
+                        size_t *bytes);
+
+/* mplu_dgetrf -- P A = L U of a real m x n A (see mplu_zgetrf). */
+int mplu_dgetrf(int prec, int64_t m, int64_t n, mplu_dmat_t A, int32_t *d_ipiv,
+                int32_t *d_info, const mplu_opts_t *opts, void *d_work, size_t work_bytes,
+                void *stream);
+
+/* mplu_dgetrs_wsbytes -- workspace bytes mplu_dgetrs needs. */
+int mplu_dgetrs_wsbytes(int prec, int64_t n, int64_t nrhs, size_t *bytes);
+
+/* mplu_dgetrs -- solve A X = B (trans 'N') or A^T X = B (trans 'T') with the factors of
+ * mplu_dgetrf (Sec. 4).  B (n x nrhs) is overwritten by X. */
+int mplu_dgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_dmat_t LU,
+                const int32_t *d_ipiv, mplu_dmat_t B, void *d_work, size_t work_bytes,
+                void *stream);
+
+/* mplu_dgesv_wsbytes -- workspace bytes mplu_dgesv needs. */
+int mplu_dgesv_wsbytes(int prec, int64_t n, int64_t nrhs, const mplu_opts_t *opts,
+                       size_t *bytes);
+
+/* mplu_dgesv -- solve the real system A X = B: mplu_dgetrf then mplu_dgetrs('N').
+ *   A (n x n) is overwritten by its factors, B (n x nrhs) by X. */
+int mplu_dgesv(int prec, int64_t n, int64_t nrhs, mplu_dmat_t A, int32_t *d_ipiv,
+               mplu_dmat_t B, int32_t *d_info, const mplu_opts_t *opts, void *d_work,
+               size_t work_bytes, void *stream);
+
+/*
+ * mplu_dgemm -- Cm := beta*Cm + alpha*op(A)*op(B) for real multi-component matrices, the
+ * real product the factorisation's trailing update uses (no workspace).
+ *   opA, opB: 'N' or 'T'.  alpha_sign: +1 or -1.  beta: 0 or 1.  Cm must not overlap A
+ *   or B.
+ */
+int mplu_dgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k,
+               int alpha_sign, mplu_dmat_t A, mplu_dmat_t B, int beta, mplu_dmat_t Cm,
+               void *stream);
+
 /* mplu_strerror -- static text for a return code. */
 const char *mplu_strerror(int code);
 

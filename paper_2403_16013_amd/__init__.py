@@ -17,6 +17,7 @@ import os
 import torch
 
 __all__ = ["lib", "renorm_", "convert", "getrf", "getrs", "gesv", "gemm", "solve",
+           "dgetrf", "dgetrs", "dgesv", "dgemm",
            "GEMM_4M", "GEMM_3M", "GEMM_SPLIT_F64", "GEMM_SPLIT_I8", "MPLUError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,6 +33,10 @@ class MPLUError(RuntimeError):
 
 
 class ZMat(ct.Structure):
+    _fields_ = [("planes", ct.c_void_p), ("ld", ct.c_int64), ("plane_stride", ct.c_int64)]
+
+
+class DMat(ct.Structure):
     _fields_ = [("planes", ct.c_void_p), ("ld", ct.c_int64), ("plane_stride", ct.c_int64)]
 
 
@@ -70,9 +75,20 @@ def lib():
                                      ct.POINTER(sz)]
     L.mplu_zgemm.argtypes = [ct.c_int, ct.c_char, ct.c_char, i64, i64, i64, ct.c_int, ZMat,
                              ZMat, ct.c_int, ZMat, ct.c_int, ct.POINTER(Opts), vp, sz, vp]
+    L.mplu_dgetrf_wsbytes.argtypes = [ct.c_int, i64, i64, ct.POINTER(Opts), ct.POINTER(sz)]
+    L.mplu_dgetrf.argtypes = [ct.c_int, i64, i64, DMat, i32p, i32p, ct.POINTER(Opts), vp, sz, vp]
+    L.mplu_dgetrs_wsbytes.argtypes = [ct.c_int, i64, i64, ct.POINTER(sz)]
+    L.mplu_dgetrs.argtypes = [ct.c_int, ct.c_char, i64, i64, DMat, i32p, DMat, vp, sz, vp]
+    L.mplu_dgesv_wsbytes.argtypes = [ct.c_int, i64, i64, ct.POINTER(Opts), ct.POINTER(sz)]
+    L.mplu_dgesv.argtypes = [ct.c_int, i64, i64, DMat, i32p, DMat, i32p, ct.POINTER(Opts), vp,
+                             sz, vp]
+    L.mplu_dgemm.argtypes = [ct.c_int, ct.c_char, ct.c_char, i64, i64, i64, ct.c_int, DMat,
+                             DMat, ct.c_int, DMat, vp]
     for name in ("mplu_zrenorm", "mplu_zconvert", "mplu_zgetrf_wsbytes", "mplu_zgetrf",
                  "mplu_zgetrs_wsbytes", "mplu_zgetrs", "mplu_zgesv_wsbytes", "mplu_zgesv",
-                 "mplu_zgemm_wsbytes", "mplu_zgemm"):
+                 "mplu_zgemm_wsbytes", "mplu_zgemm", "mplu_dgetrf_wsbytes", "mplu_dgetrf",
+                 "mplu_dgetrs_wsbytes", "mplu_dgetrs", "mplu_dgesv_wsbytes", "mplu_dgesv",
+                 "mplu_dgemm"):
         getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -202,6 +218,85 @@ def gemm(A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None, opA: 
     _check(lib().mplu_zgemm(C, opA.encode(), opB.encode(), m, n, k, int(alpha), _zmat(A),
                             _zmat(B), beta, _zmat(Cm), meth, ct.byref(o), work.data_ptr(),
                             work.numel(), _stream()), "mplu_zgemm")
+    return Cm
+
+
+# ---------------------------------------------------------------- real matrices
+# float64 CUDA tensors of shape (C, ncols, ld): plane [c] is component c, column-major,
+# so element (i, j) is T[c, j, i].
+
+def _dmat(T: torch.Tensor) -> DMat:
+    if T.dtype != torch.float64 or T.dim() != 3:
+        raise ValueError("expected a float64 tensor of shape (C, ncols, ld)")
+    if not T.is_contiguous():
+        raise ValueError("plane tensor must be contiguous")
+    if not T.is_cuda:
+        raise ValueError("plane tensor must live on the GPU")
+    return DMat(T.data_ptr(), T.shape[2], T.shape[1] * T.shape[2])
+
+
+def dgetrf(A: torch.Tensor, panel: int = 64, m: int | None = None,
+           work: torch.Tensor | None = None, lookahead: bool = True):
+    """In-place P A = L U of a real matrix.  Returns (ipiv, info) int32 device tensors."""
+    C, n = A.shape[0], A.shape[1]
+    m = A.shape[2] if m is None else m
+    o = _opts(panel, "3m", 0, 0, lookahead)
+    nb = ct.c_size_t()
+    _check(lib().mplu_dgetrf_wsbytes(C, m, n, ct.byref(o), ct.byref(nb)), "wsbytes")
+    if work is None or work.numel() < nb.value:
+        work = _work(nb.value, A.device)
+    ipiv = torch.zeros(max(1, min(m, n)), dtype=torch.int32, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(lib().mplu_dgetrf(C, m, n, _dmat(A), ipiv.data_ptr(), info.data_ptr(), ct.byref(o),
+                             work.data_ptr(), work.numel(), _stream()), "mplu_dgetrf")
+    return ipiv[: min(m, n)], info
+
+
+def dgetrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, trans: str = "N",
+           work: torch.Tensor | None = None) -> torch.Tensor:
+    """Solve A X = B ('N') or A^T X = B ('T') in place in B (real)."""
+    C, n = LU.shape[0], LU.shape[1]
+    nrhs = B.shape[1]
+    nb = ct.c_size_t()
+    _check(lib().mplu_dgetrs_wsbytes(C, n, nrhs, ct.byref(nb)), "wsbytes")
+    if work is None or work.numel() < nb.value:
+        work = _work(nb.value, LU.device)
+    ipiv = ipiv.to(torch.int32).contiguous()
+    _check(lib().mplu_dgetrs(C, trans.encode(), n, nrhs, _dmat(LU), ipiv.data_ptr(), _dmat(B),
+                             work.data_ptr(), work.numel(), _stream()), "mplu_dgetrs")
+    return B
+
+
+def dgesv(A: torch.Tensor, B: torch.Tensor, panel: int = 64, work: torch.Tensor | None = None,
+          lookahead: bool = True):
+    """Real A X = B in place: A := factors, B := X.  Returns (ipiv, info)."""
+    C, n = A.shape[0], A.shape[1]
+    nrhs = B.shape[1]
+    o = _opts(panel, "3m", 0, 0, lookahead)
+    nb = ct.c_size_t()
+    _check(lib().mplu_dgesv_wsbytes(C, n, nrhs, ct.byref(o), ct.byref(nb)), "wsbytes")
+    if work is None or work.numel() < nb.value:
+        work = _work(nb.value, A.device)
+    ipiv = torch.zeros(max(1, n), dtype=torch.int32, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(lib().mplu_dgesv(C, n, nrhs, _dmat(A), ipiv.data_ptr(), _dmat(B), info.data_ptr(),
+                            ct.byref(o), work.data_ptr(), work.numel(), _stream()), "mplu_dgesv")
+    return ipiv[:n], info
+
+
+def dgemm(A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None, opA: str = "N",
+          opB: str = "N", alpha: int = 1) -> torch.Tensor:
+    """Cm := beta Cm + alpha op(A) op(B) for real matrices (beta = 1 when Cm is given)."""
+    C = A.shape[0]
+    m = A.shape[2] if opA == "N" else A.shape[1]
+    k = A.shape[1] if opA == "N" else A.shape[2]
+    n = B.shape[1] if opB == "N" else B.shape[2]
+    beta = 1
+    if Cm is None:
+        beta = 0
+        Cm = torch.empty((C, n, m), dtype=torch.float64, device=A.device)
+    _check(lib().mplu_dgemm(C, opA.encode(), opB.encode(), m, n, k, int(alpha), _dmat(A),
+                            _dmat(B), beta, _dmat(Cm), _stream()), "mplu_dgemm")
     return Cm
 
 

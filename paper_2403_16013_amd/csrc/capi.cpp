@@ -42,6 +42,10 @@ inline int panel_width(const mplu_opts_t *o) {
 
 inline int gemm_method(const mplu_opts_t *o) { return o ? o->gemm : MPLU_GEMM_3M; }
 
+// internal trailing-update method of the real factorisation: the real product (the
+// Im = 0 case of Eq. 3m_cemm) on the real planes only
+constexpr int kGemmReal = 100;
+
 #define HIPCHK(x)                          \
   do {                                     \
     if ((x) != hipSuccess) return MPLU_E_HIP; \
@@ -144,8 +148,8 @@ hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int j
   if (is_split(method))
     return launch_gemm_split(C, method == MPLU_GEMM_SPLIT_I8, S, 'N', 'N', m - j - jb, c1 - c0,
                              jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, split_ws, s);
-  return launch_gemm(C, method == MPLU_GEMM_3M ? 1 : 0, 'N', 'N', m - j - jb, c1 - c0, jb, -1, a,
-                     j + jb, j, a, j, c0, 1, a, j + jb, c0, s);
+  return launch_gemm(C, method == kGemmReal ? 2 : (method == MPLU_GEMM_3M ? 1 : 0), 'N', 'N',
+                     m - j - jb, c1 - c0, jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, s);
 }
 
 hipError_t step_update(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
@@ -203,9 +207,15 @@ int mplu_zgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
   return getrf_ws(prec, m, n, opts, bytes);
 }
 
-int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
-                int32_t *d_info, const mplu_opts_t *opts, void *d_work, size_t work_bytes,
-                void *stream) {
+}  // extern "C"
+
+namespace {
+
+// the blocked factorisation of mplu_zgetrf; real = true runs the trailing updates with the
+// real product (the imaginary planes of A must then be zero and stay so)
+int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
+               int32_t *d_info, const mplu_opts_t *opts, void *d_work, size_t work_bytes,
+               void *stream, bool real) {
   if (!prec_ok(prec)) return -1;
   if (m < 0) return -2;
   if (n < 0) return -3;
@@ -218,6 +228,7 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M && method != MPLU_GEMM_SPLIT_F64 &&
       method != MPLU_GEMM_SPLIT_I8)
     return -7;
+  if (real && method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
   if (!split_opts_ok(prec, method, opts)) return MPLU_E_UNSUPPORTED;
   size_t need = 0;
   getrf_ws(prec, m, n, opts, &need);
@@ -241,6 +252,7 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   void *split_rest = wb + 3 * L.panel;
   void *split_next = wb + 3 * L.panel + L.split_rest;
   const int S = opts ? opts->n_slices : 0;
+  const int upd = real ? kGemmReal : method;
 
   unsigned base[3] = {0u, 0u, 0u};
   for (int i = 0; i < 3; ++i) HIPCHK(panel_ws_clear(pws[i], s));
@@ -249,7 +261,7 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
       const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
       HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, pws[0], &base[0], s));
       HIPCHK(launch_laswp(C, a, j, j + jb, n, pws[0], jb, s));
-      HIPCHK(step_update(C, method, S, a, m, j, jb, j + jb, n, split_rest, s));
+      HIPCHK(step_update(C, upd, S, a, m, j, jb, j + jb, n, split_rest, s));
     }
     return 0;
   }
@@ -279,14 +291,14 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     if (nx1 > nx0) {
       // the next panel's columns: interchanges and U12 in one launch, then the product
       HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb)));
-      HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx0, nx1, split_next, s));
+      HIPCHK(step_gemm(C, upd, S, a, m, j, jb, nx0, nx1, split_next, s));
     }
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device
     HIPCHK(hipEventRecord(sd->ev_chain, s));
     HIPCHK(step_trsm(C, a, j, jb, nx1, n, b, panel_swap_list(pw, C, jb)));
     HIPCHK(hipStreamWaitEvent(b, sd->ev_chain, 0));
-    HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx1, n, split_rest, b));
+    HIPCHK(step_gemm(C, upd, S, a, m, j, jb, nx1, n, split_rest, b));
     HIPCHK(hipEventRecord(sd->ev_rest, b));
     // panel k's interchanges on the columns left of it; the workspace holding the list is
     // next written by panel k+3, which the caller's stream starts only after the second
@@ -299,6 +311,16 @@ int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   HIPCHK(hipEventRecord(sd->ev_rest, b));
   HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mplu_zgetrf(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
+                int32_t *d_info, const mplu_opts_t *opts, void *d_work, size_t work_bytes,
+                void *stream) {
+  return getrf_core(prec, m, n, A, d_ipiv, d_info, opts, d_work, work_bytes, stream, false);
 }
 
 int mplu_zgetrs_wsbytes(int prec, int64_t n, int64_t nrhs, size_t *bytes) {
@@ -466,6 +488,190 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, in
   }
   HIPCHK(launch_gemm(prec, method == MPLU_GEMM_3M ? 1 : 0, opA, opB, m, n, k, alpha_sign, zm(A),
                      0, 0, zm(B), 0, 0, beta, zm(Cm), 0, 0, (hipStream_t)stream));
+  return 0;
+}
+
+// ------------------------------------------------------------------ real matrices
+// The Im = 0 case: a complex copy of the operands in the workspace (imaginary planes
+// zero), the complex kernels for the panels, interchanges and triangular solves, and the
+// real product for the trailing updates; the results are copied back.
+
+static inline bool dmat_ok(const mplu_dmat_t &A, int64_t rows, int64_t cols) {
+  return mat_ok(mplu_zmat_t{A.planes, A.ld, A.plane_stride}, rows, cols);
+}
+
+static inline ZM dm(const mplu_dmat_t &A) { return ZM{A.planes, A.ld, A.plane_stride}; }
+
+// a complex rows x cols matrix with ld = max(1, rows) carved at *off in the workspace
+static inline size_t zcopy_bytes(int C, int64_t rows, int64_t cols) {
+  const int64_t ld = rows > 1 ? rows : 1;
+  return align256(sizeof(double) * 2 * (size_t)C * (size_t)ld * (size_t)(cols > 0 ? cols : 0));
+}
+
+static inline mplu_zmat_t zcopy_at(char *base, size_t off, int64_t rows, int64_t cols) {
+  const int64_t ld = rows > 1 ? rows : 1;
+  return mplu_zmat_t{(double *)(base + off), ld, ld * (cols > 0 ? cols : 0)};
+}
+
+int mplu_dgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
+                        size_t *bytes) {
+  if (!prec_ok(prec)) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!bytes) return -5;
+  size_t f = 0;
+  getrf_ws(prec, m, n, opts, &f);
+  *bytes = zcopy_bytes(prec, m, n) + f;
+  return 0;
+}
+
+int mplu_dgetrf(int prec, int64_t m, int64_t n, mplu_dmat_t A, int32_t *d_ipiv,
+                int32_t *d_info, const mplu_opts_t *opts, void *d_work, size_t work_bytes,
+                void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (!dmat_ok(A, m, n)) return -4;
+  const int64_t mn = m < n ? m : n;
+  if (mn > 0 && d_ipiv == nullptr) return -5;
+  if (d_info == nullptr) return -6;
+  size_t need = 0;
+  mplu_dgetrf_wsbytes(prec, m, n, opts, &need);
+  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
+  if (work_bytes < need) return MPLU_E_WORKSPACE;
+  const size_t zb = zcopy_bytes(prec, m, n);
+  const mplu_zmat_t Z = zcopy_at((char *)d_work, 0, m, n);
+  hipStream_t s = (hipStream_t)stream;
+  // options are checked by the factorisation before anything is enqueued there; check
+  // them here first so that nothing is enqueued on an argument error
+  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -7;
+  const int method = gemm_method(opts);
+  if (method < 0 || method > 3) return -7;
+  if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
+  const int kb0 = panel_width(opts);
+  for (int64_t j = 0, kb = (mn > 0 && kb0 > mn) ? mn : kb0; j < mn; j += kb) {
+    const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
+    if (panel_geometry(prec, m - j, jb).G == 0) return MPLU_E_UNSUPPORTED;
+  }
+  HIPCHK(launch_embed(prec, m, n, dm(A), zm(Z), true, s));
+  const int rc = getrf_core(prec, m, n, Z, d_ipiv, d_info, opts, (char *)d_work + zb,
+                            work_bytes - zb, stream, true);
+  if (rc != 0) return rc;
+  HIPCHK(launch_embed(prec, m, n, dm(A), zm(Z), false, s));
+  return 0;
+}
+
+int mplu_dgetrs_wsbytes(int prec, int64_t n, int64_t nrhs, size_t *bytes) {
+  if (!prec_ok(prec)) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (!bytes) return -4;
+  size_t r = 0;
+  getrs_ws(prec, n, nrhs, &r);
+  *bytes = zcopy_bytes(prec, n, n) + zcopy_bytes(prec, n, nrhs) + r;
+  return 0;
+}
+
+int mplu_dgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_dmat_t LU,
+                const int32_t *d_ipiv, mplu_dmat_t B, void *d_work, size_t work_bytes,
+                void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (trans != 'N' && trans != 'T') return -2;
+  if (n < 0) return -3;
+  if (nrhs < 0) return -4;
+  if (!dmat_ok(LU, n, n)) return -5;
+  if (n > 0 && d_ipiv == nullptr) return -6;
+  if (!dmat_ok(B, n, nrhs)) return -7;
+  size_t need = 0;
+  mplu_dgetrs_wsbytes(prec, n, nrhs, &need);
+  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
+  if (work_bytes < need) return MPLU_E_WORKSPACE;
+  if (n == 0 || nrhs == 0) return 0;
+  if (n > INT32_MAX) return MPLU_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  char *wb = (char *)d_work;
+  const size_t zl = zcopy_bytes(prec, n, n), zr = zcopy_bytes(prec, n, nrhs);
+  const mplu_zmat_t ZL = zcopy_at(wb, 0, n, n), ZB = zcopy_at(wb, zl, n, nrhs);
+  HIPCHK(launch_embed(prec, n, n, dm(LU), zm(ZL), true, s));
+  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), true, s));
+  // A^T = A^H when the imaginary parts are zero
+  const int rc = mplu_zgetrs(prec, trans == 'N' ? 'N' : 'C', n, nrhs, ZL, d_ipiv, ZB,
+                             wb + zl + zr, work_bytes - zl - zr, stream);
+  if (rc != 0) return rc;
+  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), false, s));
+  return 0;
+}
+
+int mplu_dgesv_wsbytes(int prec, int64_t n, int64_t nrhs, const mplu_opts_t *opts,
+                       size_t *bytes) {
+  if (!prec_ok(prec)) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (!bytes) return -5;
+  size_t a = 0, b = 0;
+  getrf_ws(prec, n, n, opts, &a);
+  getrs_ws(prec, n, nrhs, &b);
+  *bytes = zcopy_bytes(prec, n, n) + zcopy_bytes(prec, n, nrhs) + (a > b ? a : b);
+  return 0;
+}
+
+int mplu_dgesv(int prec, int64_t n, int64_t nrhs, mplu_dmat_t A, int32_t *d_ipiv,
+               mplu_dmat_t B, int32_t *d_info, const mplu_opts_t *opts, void *d_work,
+               size_t work_bytes, void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (!dmat_ok(A, n, n)) return -4;
+  if (n > 0 && d_ipiv == nullptr) return -5;
+  if (!dmat_ok(B, n, nrhs)) return -6;
+  if (d_info == nullptr) return -7;
+  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -8;
+  const int method = gemm_method(opts);
+  if (method < 0 || method > 3) return -8;
+  if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
+  size_t need = 0;
+  mplu_dgesv_wsbytes(prec, n, nrhs, opts, &need);
+  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -9;
+  if (work_bytes < need) return MPLU_E_WORKSPACE;
+  const int kb0 = panel_width(opts);
+  for (int64_t j = 0, kb = (n > 0 && kb0 > n) ? n : kb0; j < n; j += kb) {
+    const int jb = (int)((n - j) < kb ? (n - j) : kb);
+    if (panel_geometry(prec, n - j, jb).G == 0) return MPLU_E_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char *wb = (char *)d_work;
+  const size_t za = zcopy_bytes(prec, n, n), zr = zcopy_bytes(prec, n, nrhs);
+  const mplu_zmat_t ZA = zcopy_at(wb, 0, n, n), ZB = zcopy_at(wb, za, n, nrhs);
+  HIPCHK(launch_embed(prec, n, n, dm(A), zm(ZA), true, s));
+  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), true, s));
+  int rc = getrf_core(prec, n, n, ZA, d_ipiv, d_info, opts, wb + za + zr,
+                      work_bytes - za - zr, stream, true);
+  if (rc != 0) return rc;
+  if (n > 0 && nrhs > 0) {
+    rc = mplu_zgetrs(prec, 'N', n, nrhs, ZA, d_ipiv, ZB, wb + za + zr, work_bytes - za - zr,
+                     stream);
+    if (rc != 0) return rc;
+  }
+  HIPCHK(launch_embed(prec, n, n, dm(A), zm(ZA), false, s));
+  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), false, s));
+  return 0;
+}
+
+int mplu_dgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, int alpha_sign,
+               mplu_dmat_t A, mplu_dmat_t B, int beta, mplu_dmat_t Cm, void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (opA != 'N' && opA != 'T') return -2;
+  if (opB != 'N' && opB != 'T') return -3;
+  if (m < 0) return -4;
+  if (n < 0) return -5;
+  if (k < 0) return -6;
+  if (alpha_sign != 1 && alpha_sign != -1) return -7;
+  if (!dmat_ok(A, opA == 'N' ? m : k, opA == 'N' ? k : m)) return -8;
+  if (!dmat_ok(B, opB == 'N' ? k : n, opB == 'N' ? n : k)) return -9;
+  if (beta != 0 && beta != 1) return -10;
+  if (!dmat_ok(Cm, m, n)) return -11;
+  HIPCHK(launch_gemm(prec, 2, opA, opB, m, n, k, alpha_sign, dm(A), 0, 0, dm(B), 0, 0, beta,
+                     dm(Cm), 0, 0, (hipStream_t)stream));
   return 0;
 }
 

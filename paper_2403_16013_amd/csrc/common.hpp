@@ -44,6 +44,21 @@ __device__ __forceinline__ void st_z(const ZM &A, int64_t i, int64_t j, const do
   }
 }
 
+// the real planes only (a real matrix, or the real part of a complex one)
+template <int C>
+__device__ __forceinline__ void ld_re(const ZM &A, int64_t i, int64_t j, double (&re)[C]) {
+  const double *b = A.p + j * A.ld + i;
+#pragma unroll
+  for (int c = 0; c < C; ++c) re[c] = b[(int64_t)c * A.ps];
+}
+
+template <int C>
+__device__ __forceinline__ void st_re(const ZM &A, int64_t i, int64_t j, const double (&re)[C]) {
+  double *b = A.p + j * A.ld + i;
+#pragma unroll
+  for (int c = 0; c < C; ++c) b[(int64_t)c * A.ps] = re[c];
+}
+
 // Output tile of this workgroup in a 1-D grid of gm x gn tiles.  Workgroups are
 // dispatched round-robin over the 8 XCDs; the remap gives each XCD a contiguous range of
 // the tile order, and that order walks 8 tile rows down before moving one tile column
@@ -83,6 +98,10 @@ struct LdsAttr {
 hipError_t launch_renorm(int C, int64_t m, int64_t n, ZM A, hipStream_t s);
 hipError_t launch_convert(int Cs, int Cd, int64_t m, int64_t n, ZM A, ZM B, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
+// real matrix R (C planes) <-> real planes of complex Z; to_complex also clears Z's
+// imaginary planes
+hipError_t launch_embed(int C, int64_t m, int64_t n, ZM R, ZM Z, bool to_complex,
+                        hipStream_t s);
 
 struct PanelGeom {
   int G;  // workgroups
@@ -119,7 +138,8 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
                        ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s,
                        const int32_t *swl = nullptr, int swstride = 0);
 
-// Cm := beta Cm + alpha op(A) op(B);  method 0 = 4M, 1 = 3M
+// Cm := beta Cm + alpha op(A) op(B);  method 0 = 4M, 1 = 3M, 2 = real (only the real
+// planes of A, B and Cm are read, only those of Cm written; 'C' acts as 'T')
 hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,
                        int alpha_sign, ZM A, int64_t ai, int64_t aj, ZM B, int64_t bi,
                        int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s);

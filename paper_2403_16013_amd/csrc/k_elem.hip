@@ -103,6 +103,21 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t *perm, int64_t n, 
   }
 }
 
+// Real matrices on the complex kernels (the Im = 0 case): to = 1 copies the C real planes
+// of R into the real planes of Z and clears Z's imaginary planes; to = 0 copies the real
+// planes of Z back into R.
+__global__ __launch_bounds__(256) void k_embed(int64_t m, int64_t n, int C, ZM R, ZM Z, int to) {
+  const int64_t planes = to ? 2 * C : C;
+  const int64_t total = m * n * planes;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % m, rest = e / m, j = rest % n, q = rest / n;
+    double *zp = Z.p + q * Z.ps + j * Z.ld + i;
+    if (!to) R.p[q * R.ps + j * R.ld + i] = *zp;
+    else *zp = (q < C) ? R.p[q * R.ps + j * R.ld + i] : 0.0;
+  }
+}
+
 static inline int grid_for(int64_t total, int threads) {
   int64_t g = (total + threads - 1) / threads;
   if (g > 65536) g = 65536;
@@ -135,6 +150,14 @@ hipError_t launch_convert(int Cs, int Cd, int64_t m, int64_t n, ZM A, ZM B, hipS
   CONV_CASE(3, 2) CONV_CASE(3, 3) CONV_CASE(3, 4)
   CONV_CASE(4, 2) CONV_CASE(4, 3) CONV_CASE(4, 4)
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_embed(int C, int64_t m, int64_t n, ZM R, ZM Z, bool to_complex,
+                        hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int g = grid_for(m * n * (to_complex ? 2 * C : C), 256);
+  hipLaunchKernelGGL(k_embed, dim3(g), dim3(256), 0, s, m, n, C, R, Z, (int)to_complex);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {

@@ -36,10 +36,12 @@ struct GemmArgs {
 constexpr int TIDY_K = 16;
 constexpr int64_t TIDY_MIN_K = 128;
 
-template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR>
+// RE: the real product (the Im = 0 case of the 3M form: only T1 = ReA ReB is formed,
+// only the real planes are read and written; the imaginary planes are never touched).
+template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR, bool RE = false>
 __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
   constexpr int NT = (BM / TM) * (BN / TN);
-  constexpr int NV = M3 ? 3 : 2;
+  constexpr int NV = RE ? 1 : (M3 ? 3 : 2);
   constexpr int SX = BN / TN;  // threads along n
   constexpr int SY = BM / TM;  // threads along m
   static_assert(TIDY_K % BK == 0, "re-levelling points must fall on slab ends");
@@ -63,7 +65,7 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[v][i][jj][c] = 0.0;
 
-  if (!M3 && g.beta) {
+  if (!M3 && !RE && g.beta) {
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -81,7 +83,7 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
       }
   }
 
-  const double asign = (!M3 && g.alpha < 0) ? -1.0 : 1.0;
+  const double asign = (!M3 && !RE && g.alpha < 0) ? -1.0 : 1.0;
 
   for (int64_t k0 = 0; k0 < g.k; k0 += BK) {
     // stage op(A)[m0 .. m0+BM) x [k0 .. k0+BK)
@@ -91,7 +93,10 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
       else { kk = e % BK; mm = e / BK; }
       const int64_t gi = m0 + mm, gt = k0 + kk;
       double re[C], im[C];
-      if (gi < g.m && gt < g.k) {
+      if (RE && gi < g.m && gt < g.k) {
+        if (g.opA == 'N') ld_re<C>(g.A, g.ai + gi, g.aj + gt, re);
+        else ld_re<C>(g.A, g.ai + gt, g.aj + gi, re);
+      } else if (gi < g.m && gt < g.k) {
         if (g.opA == 'N') ld_z<C>(g.A, g.ai + gi, g.aj + gt, re, im);
         else ld_z<C>(g.A, g.ai + gt, g.aj + gi, re, im);
         const double isg = (g.opA == 'C') ? -asign : asign;
@@ -100,6 +105,11 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
       } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) { re[c] = 0.0; im[c] = 0.0; }
+      }
+      if (RE) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sA[kk][0][c][mm] = re[c];
+        continue;
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) { sA[kk][0][c][mm] = re[c]; sA[kk][1][c][mm] = im[c]; }
@@ -117,7 +127,10 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
       else { nn = e % BN; kk = e / BN; }
       const int64_t gj = n0 + nn, gt = k0 + kk;
       double re[C], im[C];
-      if (gj < g.n && gt < g.k) {
+      if (RE && gj < g.n && gt < g.k) {
+        if (g.opB == 'N') ld_re<C>(g.B, g.bi + gt, g.bj + gj, re);
+        else ld_re<C>(g.B, g.bi + gj, g.bj + gt, re);
+      } else if (gj < g.n && gt < g.k) {
         if (g.opB == 'N') ld_z<C>(g.B, g.bi + gt, g.bj + gj, re, im);
         else ld_z<C>(g.B, g.bi + gj, g.bj + gt, re, im);
         if (g.opB == 'C') {
@@ -127,6 +140,11 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
       } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) { re[c] = 0.0; im[c] = 0.0; }
+      }
+      if (RE) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sB[kk][0][c][nn] = re[c];
+        continue;
       }
 #pragma unroll
       for (int c = 0; c < C; ++c) { sB[kk][0][c][nn] = re[c]; sB[kk][1][c][nn] = im[c]; }
@@ -153,7 +171,12 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
 #pragma unroll
           for (int c = 0; c < C; ++c) b[v][jj][c] = sB[kk][v][c][tx + jj * SX];
       }
-      if (M3) {
+      if (RE) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int jj = 0; jj < TN; ++jj) mp::mac<C>(acc[0][i][jj], a[0][i], b[0][jj]);
+      } else if (M3) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -200,6 +223,18 @@ __global__ __launch_bounds__((BM / TM) * (BN / TN)) void k_gemm(GemmArgs g) {
       const int64_t mi = m0 + ty + i * SY, nj = n0 + tx + jj * SX;
       if (mi >= g.m || nj >= g.n) continue;
       double ore[C], oim[C];
+      if (RE) {
+        // the real part of the 3M epilogue with T2 = 0 and the imaginary part left alone
+        double t1[C], lr[C];
+        mp::renorm<C>(acc[0][i][jj], t1);
+        if (g.alpha < 0) mp::neg<C>(t1, t1);
+        if (g.beta) ld_re<C>(g.Cm, g.ci + mi, g.cj + nj, lr);
+        else mp::set_zero<C>(lr);
+        mp::push_mp<C>(lr, t1);
+        mp::renorm<C>(lr, ore);
+        st_re<C>(g.Cm, g.ci + mi, g.cj + nj, ore);
+        continue;
+      }
       if (M3) {
         double t1[C], t2[C], t3[C];
         mp::renorm<C>(acc[0][i][jj], t1);
@@ -313,11 +348,11 @@ static hipError_t go_narrow(const GemmArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR>
+template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR, bool RE = false>
 static hipError_t go(const GemmArgs &a, hipStream_t s) {
   constexpr int NT = (BM / TM) * (BN / TN);
   const dim3 grid((unsigned)(((a.n + BN - 1) / BN) * ((a.m + BM - 1) / BM)));
-  hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN, UNR>), grid, dim3(NT), 0, s, a);
+  hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN, UNR, RE>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -358,6 +393,19 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
   a.opA = opA; a.opB = opB;
   a.alpha = alpha_sign; a.beta = beta;
   const bool m3 = (method == 1);
+  // products too small to give each CU a few 32 x 32 tiles (the next panel's columns in
+  // the look-ahead, the last trailing updates) take 16 x 16 tiles, one element per
+  // thread; every element still accumulates over k in the same order, so the result does
+  // not depend on the tiling
+  const bool small = ((m + 31) / 32) * ((n + 31) / 32) < 512;
+  if (method == 2) {
+    switch (C) {
+      case 2: return small ? go<2, false, 16, 16, 16, 1, 1, 2, true>(a, s) : go<2, false, 32, 32, 8, 2, 2, 2, true>(a, s);
+      case 3: return small ? go<3, false, 16, 16, 16, 1, 1, 1, true>(a, s) : go<3, false, 32, 32, 8, 2, 2, 1, true>(a, s);
+      case 4: return small ? go<4, false, 16, 16, 16, 1, 1, 1, true>(a, s) : go<4, false, 32, 32, 8, 2, 2, 1, true>(a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (!m3 && n <= 16) {
     switch (C) {
       case 2: return go_narrow<2>(a, s);
@@ -366,11 +414,6 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
     }
     return hipErrorInvalidValue;
   }
-  // products too small to give each CU a few 32 x 32 tiles (the next panel's columns in
-  // the look-ahead, the last trailing updates) take 16 x 16 tiles, one element per
-  // thread; every element still accumulates over k in the same order, so the result does
-  // not depend on the tiling
-  const bool small = ((m + 31) / 32) * ((n + 31) / 32) < 512;
   switch (C) {
     case 2:
       if (small) return m3 ? go<2, true, 16, 16, 16, 1, 1, 2>(a, s) : go<2, false, 16, 16, 16, 1, 1, 2>(a, s);

@@ -74,6 +74,30 @@ def test_argument_checks(L):
     assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 2, z, z, 0, z, 0, None, wk, 0, None) == -7
     assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 2, z, 0, None, wk, 0, None) == -10
     assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 0, z, 7, None, wk, 0, None) == -12
+    # real matrices
+    d = m.DMat(0x1000, 8, 64)
+    dnull = m.DMat(0, 8, 64)
+    assert L.mplu_dgetrf(5, 8, 8, d, ip, inf, None, wk, 1 << 30, None) == -1
+    assert L.mplu_dgetrf(2, 9, 8, d, ip, inf, None, wk, 1 << 30, None) == -4
+    assert L.mplu_dgetrf(2, 8, 8, dnull, ip, inf, None, wk, 1 << 30, None) == -4
+    assert L.mplu_dgetrf(2, 8, 8, d, None, inf, None, wk, 1 << 30, None) == -5
+    assert L.mplu_dgetrf(2, 8, 8, d, ip, None, None, wk, 1 << 30, None) == -6
+    bad = m.Opts(-1, 1, 0, 0, 0)
+    assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
+    assert L.mplu_dgesv(2, 8, 1, d, ip, d, inf, ct.byref(bad), wk, 1 << 30, None) == -8
+    split = m.Opts(64, 3, 0, 0, 0)   # the split methods have no real form
+    assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, ct.byref(split), wk, 1 << 30, None) == -102
+    assert L.mplu_dgesv(2, 8, 1, d, ip, d, inf, ct.byref(split), wk, 1 << 30, None) == -102
+    assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, None, ct.c_void_p(0x10001), 1 << 30, None) == -8
+    assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, None, wk, 16, None) == -100
+    assert L.mplu_dgetrs(2, b"C", 8, 1, d, ip, d, wk, 1 << 30, None) == -2
+    assert L.mplu_dgetrs(2, b"N", 8, 1, d, None, d, wk, 1 << 30, None) == -6
+    assert L.mplu_dgetrs(2, b"N", 8, 1, d, ip, d, wk, 16, None) == -100
+    assert L.mplu_dgesv(2, 8, 1, d, ip, d, None, None, wk, 1 << 30, None) == -7
+    assert L.mplu_dgemm(2, b"C", b"N", 4, 4, 4, 1, d, d, 0, d, None) == -2
+    assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 2, d, d, 0, d, None) == -7
+    assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 1, d, d, 2, d, None) == -10
+    assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 1, d, d, 0, dnull, None) == -11
     assert L.mplu_zrenorm(2, 8, 8, null, None) == -4
     assert L.mplu_zconvert(2, 7, 8, 8, z, z, None) == -2
 
@@ -98,3 +122,12 @@ def test_workspace_queries(L):
     assert L.mplu_zgetrs_wsbytes(2, 100, 3, ct.byref(sz)) == 0
     assert sz.value >= 100 * 3 * 4 * 8
     assert L.mplu_zgesv_wsbytes(3, 100, 3, None, ct.byref(sz)) == 0
+    # real: a complex copy of the operands plus the complex routine's workspace
+    zf, df = ct.c_size_t(), ct.c_size_t()
+    assert L.mplu_zgetrf_wsbytes(2, 300, 200, None, ct.byref(zf)) == 0
+    assert L.mplu_dgetrf_wsbytes(2, 300, 200, None, ct.byref(df)) == 0
+    assert df.value >= zf.value + 2 * 2 * 300 * 200 * 8
+    assert L.mplu_dgetrs_wsbytes(4, 100, 3, ct.byref(df)) == 0
+    assert df.value >= 2 * 4 * 100 * (100 + 3) * 8
+    assert L.mplu_dgesv_wsbytes(3, 100, 3, None, ct.byref(df)) == 0
+    assert df.value >= sz.value + 2 * 3 * 100 * (100 + 3) * 8
