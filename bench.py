@@ -243,7 +243,7 @@ def hi_abs(torch, T):
 def matmul_bench(mp, torch, synthgen, n, reps=3):
     """The complex matrix-product benchmark of Sec. 2.4: C := A B with square n x n
     operands whose leading components are uniform on [0, 1], for DD / TD / QD and each
-    product form (4M, 3M, split INT8, split FP64).  Each product is timed with HIP events
+    product form (4M, 3M, split INT8, split FP64, one level of Strassen-Winograd over 3M).  Each product is timed with HIP events
     on the stream (one warm-up, then the mean of `reps`).  Error: max over elements of
     |C - C_ref| / (|A| |B|)_ij, C_ref the quadruple-double 4M product of the same
     (exactly widened) operands; for QD this is the difference from QD 4M itself."""
@@ -255,7 +255,7 @@ def matmul_bench(mp, torch, synthgen, n, reps=3):
         mp.renorm_(B)
         ref = mp.gemm(mp.convert(A, 4), mp.convert(B, 4), None, method="4m")
         scale = hi_abs(torch, A) @ hi_abs(torch, B)
-        for meth in ("4m", "3m", "split_i8", "split_f64"):
+        for meth in ("4m", "3m", "split_i8", "split_f64", "strassen"):
             times = []
             for r in range(reps + 1):
                 e0 = torch.cuda.Event(enable_timing=True)

@@ -49,7 +49,9 @@ typedef enum {
   MPLU_GEMM_4M = 0,        /* Eq. 4m: four real products                                */
   MPLU_GEMM_3M = 1,        /* Eq. 3m_cemm: three real products plus additions           */
   MPLU_GEMM_SPLIT_F64 = 2, /* Sec. 2.3 Ozaki scheme: exact slice products on FP64 MFMA  */
-  MPLU_GEMM_SPLIT_I8 = 3   /* same split with 7-bit INT8 slices, exact INT32 sums       */
+  MPLU_GEMM_SPLIT_I8 = 3,  /* same split with 7-bit INT8 slices, exact INT32 sums       */
+  MPLU_GEMM_STRASSEN = 4   /* mplu_zgemm only ('N', 'N'): one level of Winograd's variant
+                              of Strassen's algorithm over 3M products (Sec. 2.1)        */
 } mplu_gemm_t;
 
 /* A complex multi-component matrix: see NUMBER FORMAT above. */
@@ -150,7 +152,9 @@ int mplu_zgesv(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv
                mplu_zmat_t B, int32_t *d_info, const mplu_opts_t *opts, void *d_work,
                size_t work_bytes, void *stream);
 
-/* mplu_zgemm_wsbytes -- workspace bytes mplu_zgemm needs (0 for 3M and 4M). */
+/* mplu_zgemm_wsbytes -- workspace bytes mplu_zgemm needs (0 for 3M and 4M; the split
+ * digit planes; for MPLU_GEMM_STRASSEN an m x n product and the two half-size operand
+ * sums, complex). */
 int mplu_zgemm_wsbytes(int prec, int64_t m, int64_t n, int64_t k, int method,
                        const mplu_opts_t *opts, size_t *bytes);
 
@@ -159,7 +163,9 @@ int mplu_zgemm_wsbytes(int prec, int64_t m, int64_t n, int64_t k, int method,
  * product of Sec. 2.1 (Eq. 4m / Eq. 3m_cemm) or its split form (Sec. 2.3).
  *   opA, opB: 'N', 'T' or 'C' (conjugate transpose).  op(A) is m x k, op(B) is k x n.
  *   alpha_sign: +1 or -1.  beta: 0 (Cm is overwritten) or 1 (Cm is accumulated into).
- *   method: mplu_gemm_t.  Cm must not overlap A or B.
+ *   method: mplu_gemm_t.  Cm must not overlap A or B.  MPLU_GEMM_STRASSEN takes
+ *   opA = opB = 'N' only (MPLU_E_UNSUPPORTED otherwise); its error bound is normwise
+ *   (Strassen-type), not elementwise like the other forms.  mplu_zgetrf rejects it.
  */
 int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k,
                int alpha_sign, mplu_zmat_t A, mplu_zmat_t B, int beta, mplu_zmat_t Cm,

@@ -18,14 +18,15 @@ import torch
 
 __all__ = ["lib", "renorm_", "convert", "getrf", "getrs", "gesv", "gemm", "solve",
            "dgetrf", "dgetrs", "dgesv", "dgemm",
-           "GEMM_4M", "GEMM_3M", "GEMM_SPLIT_F64", "GEMM_SPLIT_I8", "MPLUError"]
+           "GEMM_4M", "GEMM_3M", "GEMM_SPLIT_F64", "GEMM_SPLIT_I8", "GEMM_STRASSEN",
+           "MPLUError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmplu.so")
 
-GEMM_4M, GEMM_3M, GEMM_SPLIT_F64, GEMM_SPLIT_I8 = 0, 1, 2, 3
+GEMM_4M, GEMM_3M, GEMM_SPLIT_F64, GEMM_SPLIT_I8, GEMM_STRASSEN = 0, 1, 2, 3, 4
 _METHODS = {"4m": GEMM_4M, "3m": GEMM_3M, "split_f64": GEMM_SPLIT_F64,
-            "split_i8": GEMM_SPLIT_I8}
+            "split_i8": GEMM_SPLIT_I8, "strassen": GEMM_STRASSEN}
 
 
 class MPLUError(RuntimeError):

@@ -159,6 +159,85 @@ hipError_t step_update(int C, int method, int S, ZM a, int64_t m, int64_t j, int
   return step_gemm(C, method, S, a, m, j, jb, c0, c1, split_ws, s);
 }
 
+// ------------------------------------------------------------------ Strassen-Winograd
+// C := beta C + alpha A B ('N', 'N') by one level of Winograd's variant of Strassen's
+// algorithm (the paper's other fast product, Sec. 2.1) over 3M products: seven half-size
+// complex products and fifteen matrix sums instead of eight products.  One level only:
+// at the sizes this GPU runs, the half-size products still fill the device, quarter-size
+// ones would not.  Odd sizes are peeled: the even leading part goes through the
+// recursion and the last row, column and k term are plain 3M products.
+//
+// Workspace: W (m x n, the product), X (m/2 x k/2), Y (k/2 x n/2), complex.
+
+inline ZM zsub(ZM a, int64_t i, int64_t j) { return ZM{a.p + j * a.ld + i, a.ld, a.ps}; }
+
+inline size_t zmat_bytes(int C, int64_t r, int64_t c) {
+  return align256(sizeof(double) * 2 * (size_t)C * (size_t)(r > 1 ? r : 1) * (size_t)(c > 0 ? c : 0));
+}
+
+size_t strassen_ws(int C, int64_t m, int64_t n, int64_t k) {
+  return zmat_bytes(C, m, n) + zmat_bytes(C, m / 2, k / 2) + zmat_bytes(C, k / 2, n / 2);
+}
+
+// product on sub-blocks: O := beta O + alpha A B (3M)
+inline hipError_t g3m(int C, int64_t m, int64_t n, int64_t k, int alpha, ZM A, ZM B, int beta,
+                      ZM O, hipStream_t s) {
+  return launch_gemm(C, 1, 'N', 'N', m, n, k, alpha, A, 0, 0, B, 0, 0, beta, O, 0, 0, s);
+}
+
+hipError_t strassen_zgemm(int C, int64_t m, int64_t n, int64_t k, int alpha, ZM A, ZM B,
+                          int beta, ZM Cm, void *ws, hipStream_t s) {
+  if (m == 0 || n == 0) return hipSuccess;
+  char *wb = (char *)ws;
+  const int64_t ldw = m > 1 ? m : 1;
+  const ZM W{(double *)wb, ldw, ldw * n};
+  const int64_t h = m / 2, q = n / 2, r = k / 2;  // half sizes
+  const ZM X{(double *)(wb + zmat_bytes(C, m, n)), h > 1 ? h : 1, (h > 1 ? h : 1) * r};
+  const ZM Y{(double *)(wb + zmat_bytes(C, m, n) + zmat_bytes(C, h, r)), r > 1 ? r : 1,
+             (r > 1 ? r : 1) * q};
+  hipError_t e;
+#define GO(x)                              \
+  do {                                     \
+    if ((e = (x)) != hipSuccess) return e; \
+  } while (0)
+  if (h > 0 && q > 0 && r > 0) {
+    const ZM A11 = A, A12 = zsub(A, 0, r), A21 = zsub(A, h, 0), A22 = zsub(A, h, r);
+    const ZM B11 = B, B12 = zsub(B, 0, q), B21 = zsub(B, r, 0), B22 = zsub(B, r, q);
+    const ZM W11 = W, W12 = zsub(W, 0, q), W21 = zsub(W, h, 0), W22 = zsub(W, h, q);
+    GO(launch_zaxpby(C, h, r, 1, A11, -1, A21, X, s));     // X = S3 = A11 - A21
+    GO(launch_zaxpby(C, r, q, 1, B22, -1, B12, Y, s));     // Y = T3 = B22 - B12
+    GO(g3m(C, h, q, r, 1, X, Y, 0, W21, s));               // W21 = P7 = S3 T3
+    GO(launch_zaxpby(C, h, r, 1, A21, 1, A22, X, s));      // X = S1 = A21 + A22
+    GO(launch_zaxpby(C, r, q, 1, B12, -1, B11, Y, s));     // Y = T1 = B12 - B11
+    GO(g3m(C, h, q, r, 1, X, Y, 0, W22, s));               // W22 = P5 = S1 T1
+    GO(launch_zaxpby(C, h, r, 1, X, -1, A11, X, s));       // X = S2 = S1 - A11
+    GO(launch_zaxpby(C, r, q, 1, B22, -1, Y, Y, s));       // Y = T2 = B22 - T1
+    GO(g3m(C, h, q, r, 1, X, Y, 0, W12, s));               // W12 = P6 = S2 T2
+    GO(launch_zaxpby(C, h, r, 1, A12, -1, X, X, s));       // X = S4 = A12 - S2
+    GO(g3m(C, h, q, r, 1, A11, B11, 0, W11, s));           // W11 = P1 = A11 B11
+    GO(launch_zaxpby(C, h, q, 1, W12, 1, W11, W12, s));    // W12 = U2 = P6 + P1
+    GO(launch_zaxpby(C, h, q, 1, W21, 1, W12, W21, s));    // W21 = U3 = P7 + U2
+    GO(launch_zaxpby(C, h, q, 1, W12, 1, W22, W12, s));    // W12 = U4 = U2 + P5
+    GO(launch_zaxpby(C, h, q, 1, W22, 1, W21, W22, s));    // W22 = C22 = P5 + U3
+    GO(g3m(C, h, q, r, 1, X, B22, 1, W12, s));             // W12 = C12 = U4 + S4 B22
+    GO(launch_zaxpby(C, r, q, 1, Y, -1, B21, Y, s));       // Y = T4 = T2 - B21
+    GO(g3m(C, h, q, r, -1, A22, Y, 1, W21, s));            // W21 = C21 = U3 - A22 T4
+    GO(g3m(C, h, q, r, 1, A12, B21, 1, W11, s));           // W11 = C11 = P1 + A12 B21
+    if (k % 2)  // the last k term of the even leading part
+      GO(g3m(C, 2 * h, 2 * q, 1, 1, zsub(A, 0, k - 1), zsub(B, k - 1, 0), 1, W, s));
+  } else if (h > 0 && q > 0) {  // k < 2: a plain product of the even leading part
+    GO(g3m(C, 2 * h, 2 * q, k, 1, A, B, 0, W, s));
+  }
+  if (n % 2)  // last column, all rows
+    GO(g3m(C, m, 1, k, 1, A, zsub(B, 0, n - 1), 0, zsub(W, 0, n - 1), s));
+  if (m % 2 && q > 0)  // last row, the even leading columns
+    GO(g3m(C, 1, 2 * q, k, 1, zsub(A, m - 1, 0), B, 0, zsub(W, m - 1, 0), s));
+  // C := beta C + alpha W
+  GO(launch_zaxpby(C, m, n, beta, Cm, alpha, W, Cm, s));
+#undef GO
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -451,11 +530,12 @@ int mplu_zgemm_wsbytes(int prec, int64_t m, int64_t n, int64_t k, int method,
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (k < 0) return -4;
-  if (method < 0 || method > 3) return -5;
+  if (method < 0 || method > MPLU_GEMM_STRASSEN) return -5;
   if (!bytes) return -7;
   *bytes = is_split(method) ? split_ws_bytes(prec, method == MPLU_GEMM_SPLIT_I8, m, n, k,
                                              opts ? opts->n_slices : 0)
-                            : 0;
+           : method == MPLU_GEMM_STRASSEN ? strassen_ws(prec, m, n, k)
+                                          : 0;
   return 0;
 }
 
@@ -473,8 +553,18 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, in
   if (!mat_ok(B, opB == 'N' ? k : n, opB == 'N' ? n : k)) return -9;
   if (beta != 0 && beta != 1) return -10;
   if (!mat_ok(Cm, m, n)) return -11;
-  if (method < 0 || method > 3) return -12;
+  if (method < 0 || method > MPLU_GEMM_STRASSEN) return -12;
   if (opts && opts->flags != 0) return -13;
+  if (method == MPLU_GEMM_STRASSEN) {
+    if (opA != 'N' || opB != 'N') return MPLU_E_UNSUPPORTED;
+    size_t need = 0;
+    mplu_zgemm_wsbytes(prec, m, n, k, method, opts, &need);
+    if (m > 0 && n > 0 && (d_work == nullptr || ((uintptr_t)d_work & 255u))) return -14;
+    if (work_bytes < need) return MPLU_E_WORKSPACE;
+    HIPCHK(strassen_zgemm(prec, m, n, k, alpha_sign, zm(A), zm(B), beta, zm(Cm), d_work,
+                          (hipStream_t)stream));
+    return 0;
+  }
   if (is_split(method)) {
     if (!split_opts_ok(prec, method, opts)) return MPLU_E_UNSUPPORTED;
     size_t need = 0;

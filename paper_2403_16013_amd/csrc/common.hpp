@@ -98,6 +98,9 @@ struct LdsAttr {
 hipError_t launch_renorm(int C, int64_t m, int64_t n, ZM A, hipStream_t s);
 hipError_t launch_convert(int Cs, int Cd, int64_t m, int64_t n, ZM A, ZM B, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
+// O := sa A + sb B (complex, m x n, sa and sb in {-1, 0, 1}); O may alias A or B
+hipError_t launch_zaxpby(int C, int64_t m, int64_t n, int sa, ZM A, int sb, ZM B, ZM O,
+                         hipStream_t s);
 // real matrix R (C planes) <-> real planes of complex Z; to_complex also clears Z's
 // imaginary planes
 hipError_t launch_embed(int C, int64_t m, int64_t n, ZM R, ZM Z, bool to_complex,

@@ -118,6 +118,38 @@ __global__ __launch_bounds__(256) void k_embed(int64_t m, int64_t n, int C, ZM R
   }
 }
 
+// O := sa A + sb B for complex matrices (sa, sb in {-1, 0, 1}; a zero coefficient drops
+// the term), one rounding per part; O may be A or B (each element is read before it is
+// written by the same thread).  The matrix sums of Winograd's variant of Strassen's
+// algorithm and the final C := beta C + alpha W.
+template <int C>
+__global__ __launch_bounds__(256) void k_zaxpby(int64_t m, int64_t n, int sa, ZM A, int sb, ZM B,
+                                                ZM O) {
+  const int64_t total = m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % m, j = e / m;
+    double lr[C], li[C];
+    mp::set_zero<C>(lr);
+    mp::set_zero<C>(li);
+    double xr[C], xi[C];
+    if (sa != 0) {
+      ld_z<C>(A, i, j, xr, xi);
+      if (sa > 0) { mp::push_mp<C>(lr, xr); mp::push_mp<C>(li, xi); }
+      else { mp::push_mp_neg<C>(lr, xr); mp::push_mp_neg<C>(li, xi); }
+    }
+    if (sb != 0) {
+      ld_z<C>(B, i, j, xr, xi);
+      if (sb > 0) { mp::push_mp<C>(lr, xr); mp::push_mp<C>(li, xi); }
+      else { mp::push_mp_neg<C>(lr, xr); mp::push_mp_neg<C>(li, xi); }
+    }
+    double orr[C], oi[C];
+    mp::renorm<C>(lr, orr);
+    mp::renorm<C>(li, oi);
+    st_z<C>(O, i, j, orr, oi);
+  }
+}
+
 static inline int grid_for(int64_t total, int threads) {
   int64_t g = (total + threads - 1) / threads;
   if (g > 65536) g = 65536;
@@ -157,6 +189,19 @@ hipError_t launch_embed(int C, int64_t m, int64_t n, ZM R, ZM Z, bool to_complex
   if (m <= 0 || n <= 0) return hipSuccess;
   const int g = grid_for(m * n * (to_complex ? 2 * C : C), 256);
   hipLaunchKernelGGL(k_embed, dim3(g), dim3(256), 0, s, m, n, C, R, Z, (int)to_complex);
+  return hipGetLastError();
+}
+
+hipError_t launch_zaxpby(int C, int64_t m, int64_t n, int sa, ZM A, int sb, ZM B, ZM O,
+                         hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int g = grid_for(m * n, 256);
+  switch (C) {
+    case 2: hipLaunchKernelGGL(k_zaxpby<2>, dim3(g), dim3(256), 0, s, m, n, sa, A, sb, B, O); break;
+    case 3: hipLaunchKernelGGL(k_zaxpby<3>, dim3(g), dim3(256), 0, s, m, n, sa, A, sb, B, O); break;
+    case 4: hipLaunchKernelGGL(k_zaxpby<4>, dim3(g), dim3(256), 0, s, m, n, sa, A, sb, B, O); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

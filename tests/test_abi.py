@@ -98,6 +98,12 @@ def test_argument_checks(L):
     assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 2, d, d, 0, d, None) == -7
     assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 1, d, d, 2, d, None) == -10
     assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 1, d, d, 0, dnull, None) == -11
+    # Strassen-Winograd: 'N', 'N' products only, not a trailing-update choice
+    assert L.mplu_zgemm(2, b"T", b"N", 4, 4, 4, 1, z, z, 0, z, 4, None, wk, 1 << 30, None) == -102
+    assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 0, z, 4, None, wk, 16, None) == -100
+    assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 0, z, 5, None, wk, 0, None) == -12
+    st = m.Opts(64, 4, 0, 0, 0)
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(st), wk, 1 << 30, None) == -7
     assert L.mplu_zrenorm(2, 8, 8, null, None) == -4
     assert L.mplu_zconvert(2, 7, 8, 8, z, z, None) == -2
 
@@ -122,6 +128,9 @@ def test_workspace_queries(L):
     assert L.mplu_zgetrs_wsbytes(2, 100, 3, ct.byref(sz)) == 0
     assert sz.value >= 100 * 3 * 4 * 8
     assert L.mplu_zgesv_wsbytes(3, 100, 3, None, ct.byref(sz)) == 0
+    # Strassen-Winograd: the m x n product and two half-size operand sums
+    assert L.mplu_zgemm_wsbytes(3, 100, 80, 60, 4, None, ct.byref(g)) == 0
+    assert g.value >= 2 * 3 * 8 * (100 * 80 + 50 * 30 + 30 * 40)
     # real: a complex copy of the operands plus the complex routine's workspace
     zf, df = ct.c_size_t(), ct.c_size_t()
     assert L.mplu_zgetrf_wsbytes(2, 300, 200, None, ct.byref(zf)) == 0

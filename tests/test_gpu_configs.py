@@ -295,7 +295,8 @@ def test_matmul_paper_workload_n2048_sampled(mp, orc, C):
     leading components uniform on [0, 1]) in every product form: a 24 x 24 block of
     sampled rows and columns of each GPU product against the oracle's product of the same
     rows and columns, elementwise within 4 (n + 4) u sum |a||b| (plus the slicing term of
-    the split forms, 2^-(53C+2) below each row / column maximum)."""
+    the split forms, 2^-(53C+2) below each row / column maximum; Strassen-Winograd within
+    its normwise bound)."""
     import torch
 
     n = 2048
@@ -312,13 +313,17 @@ def test_matmul_paper_workload_n2048_sampled(mp, orc, C):
     slicing = 16 * n * 2.0 ** (-53 * C - 2) * np.outer(
         (np.abs(A[0, 0]) + np.abs(A[1, 0])).T.max(axis=1)[rows],
         (np.abs(B[0, 0]) + np.abs(B[1, 0])).T.max(axis=0)[cols])
+    amax = (np.abs(A[0, 0]) + np.abs(A[1, 0])).max()
+    bmax = (np.abs(B[0, 0]) + np.abs(B[1, 0])).max()
     Ad, Bd = to_dev(A), to_dev(B)
     worst = {}
-    for method in ("4m", "3m", "split_i8", "split_f64"):
+    for method in ("4m", "3m", "split_i8", "split_f64", "strassen"):
         ref = orc.gemm(As, Bs, None, method=4 if method == "4m" else 3, threads=0)
         got = to_host(mp.gemm(Ad, Bd, None, method=method))[:, :, cols][:, :, :, rows]
         d = orc.diff(np.ascontiguousarray(got), ref)
         tol = 4 * (n + 4) * U_FMT[C] * S + (slicing if method.startswith("split") else 0)
+        if method == "strassen":   # normwise (one Winograd level): 64 (n + 4) u n max|a| max|b|
+            tol = 64 * (n + 4) * U_FMT[C] * n * amax * bmax
         assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol), method
         worst[method] = float(np.max(np.abs(d) / S))
     record("matmul_n2048", C=C, err_over_sum_abs=worst)

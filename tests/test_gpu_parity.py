@@ -476,3 +476,51 @@ def test_matmul_uniform01_square_vs_oracle(mp, orc, C, method):
     d = orc.diff(got, ref)
     tol = (split_tol if method in SPLIT else gemm_tol)(A, B, None, "N", "N", C, n)
     assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)
+
+
+def strassen_tol(A, B, Cm, C, k):
+    """Normwise bound for one level of Winograd's variant over 3M products: the half-size
+    operand sums are at most 3 max|a| (3 max|b|) in cabs1, each sub-product is accurate
+    to 4 (k/2 + 4) u (k/2) times their maxima, and at most six matrix sums follow; every
+    entry is within 64 (k + 4) u (k max|a| max|b| + |c|)."""
+    from helpers import cabs1_hi
+
+    t = 64 * (k + 4) * U_FMT[C] * k * cabs1_hi(A).max() * cabs1_hi(B).max()
+    if Cm is not None:
+        t = t + 64 * (k + 4) * U_FMT[C] * cabs1_hi(Cm)
+    return t
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("shape", [(64, 64, 64), (150, 150, 150), (71, 45, 37), (1, 5, 3),
+                                   (5, 1, 4), (33, 34, 1)])
+def test_strassen_vs_oracle(mp, orc, C, shape):
+    m, n, k = shape
+    A = orc.canon(synthgen.uniform(m, k, C, 100))
+    B = orc.canon(synthgen.uniform(k, n, C, 101))
+    Cm = orc.canon(synthgen.uniform(m, n, C, 102))
+    for alpha, use_c in ((1, False), (-1, True), (1, True)):
+        ref = orc.gemm(A, B, Cm if use_c else None, method=3, alpha_sign=alpha)
+        got = to_host(mp.gemm(to_dev(A), to_dev(B), to_dev(Cm) if use_c else None, alpha=alpha,
+                              method="strassen"))
+        d = orc.diff(got, ref)
+        tol = strassen_tol(A, B, Cm if use_c else None, C, k)
+        assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)
+
+
+@pytest.mark.parametrize("C", CS)
+def test_strassen_exact_on_dyadic_data(mp, C):
+    """On small dyadic data every matrix sum and product of the Winograd schedule is exact,
+    so the result equals the exact product bit for bit (a wrong block, sign or peeling
+    step would show as an error of the size of the entries)."""
+    rng = np.random.default_rng(8)
+    for (m, n, k) in ((67, 41, 130), (64, 64, 65), (2, 2, 2)):
+        Ac = (rng.integers(-99, 100, (m, k)) + 1j * rng.integers(-99, 100, (m, k))) / 8
+        Bc = (rng.integers(-99, 100, (k, n)) + 1j * rng.integers(-99, 100, (k, n))) / 8
+        Cc = (rng.integers(-99, 100, (m, n)) + 1j * rng.integers(-99, 100, (m, n))) / 8
+        Td = to_dev(synthgen.planes_from_complex(Cc, C))
+        mp.gemm(to_dev(synthgen.planes_from_complex(Ac, C)),
+                to_dev(synthgen.planes_from_complex(Bc, C)), Td, alpha=-1, method="strassen")
+        got = to_host(Td)
+        assert np.array_equal((got[0, 0] + 1j * got[1, 0]).T, Cc - Ac @ Bc)
+        assert not np.any(got[:, 1:])
