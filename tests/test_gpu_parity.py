@@ -524,3 +524,26 @@ def test_strassen_exact_on_dyadic_data(mp, C):
         got = to_host(Td)
         assert np.array_equal((got[0, 0] + 1j * got[1, 0]).T, Cc - Ac @ Bc)
         assert not np.any(got[:, 1:])
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["3m", "4m"])
+def test_long_product_independent_of_tiling(mp, orc, C, method):
+    """Products deeper than 128 re-level their accumulators at the same steps of k in
+    every kernel: a block of a large product (32 x 32 tiles) equals the same block computed
+    alone (16 x 16 tiles, and for 4M with few columns the narrow kernel) bit for bit."""
+    import torch
+
+    m = n = 720   # 23 x 23 = 529 tiles of 32 x 32: the large-product kernel
+    k = 300
+    A = orc.canon(synthgen.uniform(m, k, C, 110))
+    B = orc.canon(synthgen.uniform(k, n, C, 111))
+    Cm = orc.canon(synthgen.uniform(m, n, C, 112))
+    Ad, Bd = to_dev(A), to_dev(B)
+    big = to_host(mp.gemm(Ad, Bd, to_dev(Cm), alpha=-1, method=method))
+    for (r0, c0, mr, nc) in ((37, 101, 90, 70), (500, 3, 64, 12), (0, 700, 720, 20)):
+        As = torch.from_numpy(np.ascontiguousarray(A[:, :, :, r0:r0 + mr])).cuda()
+        Bs = torch.from_numpy(np.ascontiguousarray(B[:, :, c0:c0 + nc, :])).cuda()
+        Cs = torch.from_numpy(np.ascontiguousarray(Cm[:, :, c0:c0 + nc, r0:r0 + mr])).cuda()
+        small = to_host(mp.gemm(As, Bs, Cs, alpha=-1, method=method))
+        assert np.array_equal(small, big[:, :, c0:c0 + nc, r0:r0 + mr])
