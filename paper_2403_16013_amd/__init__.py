@@ -17,6 +17,7 @@ import os
 import torch
 
 __all__ = ["lib", "renorm_", "convert", "getrf", "getrs", "gesv", "gemm", "solve",
+           "lu_factor", "lu_solve",
            "dgetrf", "dgetrs", "dgesv", "dgemm",
            "GEMM_4M", "GEMM_3M", "GEMM_SPLIT_F64", "GEMM_SPLIT_I8", "GEMM_STRASSEN",
            "MPLUError"]
@@ -301,4 +302,4 @@ def dgemm(A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None, opA:
     return Cm
 
 
-from .autograd import solve  # noqa: E402  (needs the functions above)
+from .autograd import lu_factor, lu_solve, solve  # noqa: E402  (needs the functions above)

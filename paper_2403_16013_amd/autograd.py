@@ -42,10 +42,38 @@ class MPSolve(torch.autograd.Function):
 
 def solve(A: torch.Tensor, B: torch.Tensor, panel: int = 64, method="3m",
           check_errors: bool = False) -> torch.Tensor:
-    """X = A^-1 B on plane tensors, differentiable in A and B."""
-    X = MPSolve.apply(A, B, panel, method)
+    """X = A^-1 B on plane tensors, differentiable in A and B.  With check_errors, an
+    exactly singular A (a zero pivot, info > 0) raises torch.linalg.LinAlgError after the
+    one synchronisation that reading info takes."""
+    if torch.is_grad_enabled() and (A.requires_grad or B.requires_grad):
+        X = MPSolve.apply(A, B, panel, method)
+        info = X.grad_fn.info
+    else:
+        from . import gesv
+
+        X = B.detach().clone()
+        _, info = gesv(A.detach().clone(), X, panel=panel, method=method)
     if check_errors:
-        info = int(X.grad_fn.info.item()) if X.grad_fn is not None else 0
-        if info > 0:
-            raise torch.linalg.LinAlgError(f"exactly singular: zero pivot in column {info}")
+        k = int(info.item())
+        if k > 0:
+            raise torch.linalg.LinAlgError(f"exactly singular: zero pivot in column {k}")
     return X
+
+
+def lu_factor(A: torch.Tensor, panel: int = 64, method="3m"):
+    """(LU, piv, info) of a plane tensor A, which is left unchanged (torch.linalg
+    lu_factor style: piv is 1-based, LAPACK order)."""
+    from . import getrf
+
+    LU = A.detach().clone()
+    piv, info = getrf(LU, panel=panel, method=method)
+    return LU, piv, info
+
+
+def lu_solve(LU: torch.Tensor, piv: torch.Tensor, B: torch.Tensor,
+             adjoint: bool = False) -> torch.Tensor:
+    """X = A^-1 B (or A^-H B with adjoint) from lu_factor's output; B is left unchanged."""
+    from . import getrs
+
+    X = B.detach().clone()
+    return getrs(LU, piv, X, trans="C" if adjoint else "N")

@@ -547,3 +547,33 @@ def test_long_product_independent_of_tiling(mp, orc, C, method):
         Cs = torch.from_numpy(np.ascontiguousarray(Cm[:, :, c0:c0 + nc, r0:r0 + mr])).cuda()
         small = to_host(mp.gemm(As, Bs, Cs, alpha=-1, method=method))
         assert np.array_equal(small, big[:, :, c0:c0 + nc, r0:r0 + mr])
+
+
+def test_solve_api_and_singular_check(mp, orc):
+    """lu_factor / lu_solve leave their inputs alone and agree with gesv; solve with
+    check_errors raises on an exactly singular matrix with and without autograd."""
+    import torch
+
+    n, C = 70, 2
+    A = orc.canon(synthgen.uniform(n, n, C, 120))
+    B = orc.canon(synthgen.uniform(n, 3, C, 121))
+    Ad, Bd = to_dev(A), to_dev(B)
+    LU, piv, info = mp.lu_factor(Ad)
+    X = mp.lu_solve(LU, piv, Bd)
+    XH = mp.lu_solve(LU, piv, Bd, adjoint=True)
+    assert np.array_equal(to_host(Ad), A) and np.array_equal(to_host(Bd), B)
+    A2, B2 = to_dev(A), to_dev(B)
+    mp.gesv(A2, B2)
+    assert np.array_equal(to_host(X), to_host(B2))
+    LUo, ipo, _ = orc.getf2(A)
+    XHo = orc.getrs(LUo, ipo, B, "C")
+    kappa = float(np.real(np.linalg.cond(orc.hi_complex(A), np.inf)))
+    d = orc.diff(to_host(XH), XHo)
+    assert np.abs(d).max() / np.abs(orc.hi_complex(XHo)).max() <= 10 * n * kappa * U_FMT[C]
+    assert np.array_equal(to_host(mp.solve(Ad, Bd, check_errors=True)), to_host(X))
+    S = A.copy()
+    S[:, :, 5, :] = 0.0
+    for grad in (False, True):
+        Sd = to_dev(S).requires_grad_(grad)
+        with pytest.raises(torch.linalg.LinAlgError):
+            mp.solve(Sd, to_dev(B), check_errors=True)
