@@ -577,3 +577,21 @@ def test_solve_api_and_singular_check(mp, orc):
         Sd = to_dev(S).requires_grad_(grad)
         with pytest.raises(torch.linalg.LinAlgError):
             mp.solve(Sd, to_dev(B), check_errors=True)
+
+
+def test_strassen_empty_and_k0(mp, orc):
+    """Degenerate Strassen-Winograd products: m = 0 leaves nothing to do; k = 0 gives
+    beta C (here C itself with beta = 1, zeros with beta = 0)."""
+    import torch
+
+    C = 2
+    Cm = orc.canon(synthgen.uniform(6, 4, C, 130))
+    A = torch.zeros((2, C, 0, 6), dtype=torch.float64, device="cuda")
+    B = torch.zeros((2, C, 4, 0), dtype=torch.float64, device="cuda")
+    got = to_host(mp.gemm(A, B, to_dev(Cm), k=0, method="strassen"))
+    assert np.array_equal(got, Cm)
+    got0 = to_host(mp.gemm(A, B, None, k=0, method="strassen"))
+    assert not np.any(got0)
+    E = torch.zeros((2, C, 3, 0), dtype=torch.float64, device="cuda")
+    F = torch.zeros((2, C, 0, 3), dtype=torch.float64, device="cuda")
+    assert mp.gemm(E, F, None, m=0, method="strassen").numel() == 0

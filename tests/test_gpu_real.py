@@ -210,3 +210,24 @@ def test_real_dd_n4096_backward_error(mp, orc):
     assert int(info.item()) == 0
     eta = orc.backward_error(embed(A), embed(host(Bd)), b)
     assert eta <= 10 * n * U_FMT[C], eta
+
+
+def test_real_empty_and_tiny(mp, orc):
+    import torch
+
+    # n = 0: nothing to do, info 0
+    A0 = torch.zeros((2, 0, 1), dtype=torch.float64, device="cuda")
+    B0 = torch.zeros((2, 1, 1), dtype=torch.float64, device="cuda")
+    _, info = mp.dgesv(A0, B0[:, :0, :0].contiguous())
+    assert int(info.item()) == 0
+    # 1 x 1: x = b / a
+    for C in CS:
+        A = real_planes(1, 1, C, 90 + C, orc)
+        B = real_planes(1, 1, C, 95 + C, orc)
+        Ad, Bd = dev(A), dev(B)
+        ipiv, info = mp.dgesv(Ad, Bd)
+        sync()
+        assert int(info.item()) == 0 and int(ipiv.item()) == 1
+        Xo = orc.getrs(*orc.getf2(embed(A))[:2], embed(B))
+        d = orc.diff(embed(host(Bd)), Xo)
+        assert np.abs(d).max() <= 8 * U_FMT[C] * np.abs(orc.hi_complex(Xo)).max()
