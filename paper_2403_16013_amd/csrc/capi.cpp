@@ -625,6 +625,12 @@ int mplu_dgetrf(int prec, int64_t m, int64_t n, mplu_dmat_t A, int32_t *d_ipiv,
   const int64_t mn = m < n ? m : n;
   if (mn > 0 && d_ipiv == nullptr) return -5;
   if (d_info == nullptr) return -6;
+  // the factorisation checks the options again, but only after the copy is enqueued;
+  // check them here so that nothing is enqueued on an argument error
+  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -7;
+  const int method = gemm_method(opts);
+  if (method < 0 || method > 3) return -7;
+  if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
   size_t need = 0;
   mplu_dgetrf_wsbytes(prec, m, n, opts, &need);
   if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
@@ -632,12 +638,6 @@ int mplu_dgetrf(int prec, int64_t m, int64_t n, mplu_dmat_t A, int32_t *d_ipiv,
   const size_t zb = zcopy_bytes(prec, m, n);
   const mplu_zmat_t Z = zcopy_at((char *)d_work, 0, m, n);
   hipStream_t s = (hipStream_t)stream;
-  // options are checked by the factorisation before anything is enqueued there; check
-  // them here first so that nothing is enqueued on an argument error
-  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -7;
-  const int method = gemm_method(opts);
-  if (method < 0 || method > 3) return -7;
-  if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
   const int kb0 = panel_width(opts);
   for (int64_t j = 0, kb = (mn > 0 && kb0 > mn) ? mn : kb0; j < mn; j += kb) {
     const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
