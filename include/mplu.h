@@ -180,14 +180,14 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k,
  * planes + c*plane_stride, each column-major (element (i, j) at [j*ld + i]).
  *
  * mplu_dgetrf / mplu_dgetrs / mplu_dgesv take a complex copy of their operands in the
- * workspace (imaginary planes zero) and run the complex panels, interchanges and
- * triangular solves on it, with the trailing updates done by the real product (only
- * T1 = Re(L21) Re(U12) of Eq. 3m_cemm, real planes only); the results are copied back.
- * Factors, pivots and solutions are bitwise those of the complex routines with the 3M
- * update on the same matrix with zero imaginary parts.  opts->gemm must be MPLU_GEMM_4M
- * or MPLU_GEMM_3M (both select the real product); the split methods return
- * MPLU_E_UNSUPPORTED.  Argument meaning, pivots, d_info, ownership and errors are as for
- * the complex routines; the pivot measure is |a| in full precision.
+ * workspace (imaginary planes zero).  The panels work on the real planes only (pivot
+ * measure |a| in full precision, real reciprocal), the trailing updates use the real
+ * product (only T1 = Re(L21) Re(U12) of Eq. 3m_cemm), and the interchanges and
+ * triangular solves are the complex kernels on the copy, whose imaginary parts stay
+ * zero; the results are copied back.  opts->gemm must be MPLU_GEMM_4M or MPLU_GEMM_3M
+ * (both select the real product); the split methods return MPLU_E_UNSUPPORTED.
+ * Argument meaning, pivots, d_info, ownership and errors are as for the complex
+ * routines.
  */
 typedef struct {
   double *planes;

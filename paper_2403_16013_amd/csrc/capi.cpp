@@ -338,7 +338,7 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   if (opts && (opts->flags & MPLU_FLAG_NO_LOOKAHEAD)) {
     for (int64_t j = 0; j < mn; j += kb) {
       const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
-      HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, pws[0], &base[0], s));
+      HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, pws[0], &base[0], s, real));
       HIPCHK(launch_laswp(C, a, j, j + jb, n, pws[0], jb, s));
       HIPCHK(step_update(C, upd, S, a, m, j, jb, j + jb, n, split_rest, s));
     }
@@ -357,7 +357,8 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   SideStream *sd = side_stream();
   if (!sd) return MPLU_E_HIP;
   const hipStream_t b = sd->s;
-  HIPCHK(launch_panel(C, a, 0, m, (int)(mn < kb ? mn : kb), d_ipiv, d_info, pws[0], &base[0], s));
+  HIPCHK(launch_panel(C, a, 0, m, (int)(mn < kb ? mn : kb), d_ipiv, d_info, pws[0], &base[0], s,
+                      real));
   int k = 0;
   for (int64_t j = 0; j < mn; j += kb, ++k) {
     const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
@@ -385,7 +386,7 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     HIPCHK(launch_laswp(C, a, j, n, n, pw, jb, b));
     if (nx1 > nx0)
       HIPCHK(launch_panel(C, a, nx0, m, (int)(nx1 - nx0), d_ipiv, d_info, pws[(k + 1) % 3],
-                          &base[(k + 1) % 3], s));
+                          &base[(k + 1) % 3], s, real));
   }
   HIPCHK(hipEventRecord(sd->ev_rest, b));
   HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));

@@ -121,8 +121,11 @@ hipError_t panel_ws_clear(void *ws, hipStream_t s);
 // factor rows [j, m) x columns [j, j+kb) in place; writes ipiv[j..j+kb), info, and the
 // swap list for the other columns into the workspace.  *base: barrier arrivals already
 // counted on this workspace since it was cleared; advanced past this panel's.
+// real = true: A's first C planes hold a real matrix and only those are read or written
+// (pivot |a|, real reciprocal)
 hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
-                        int32_t *info, void *ws, unsigned *base, hipStream_t s);
+                        int32_t *info, void *ws, unsigned *base, hipStream_t s,
+                        bool real = false);
 // apply the swap list left by launch_panel to columns [0, c0) and [c1, n)
 hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
                         int kb, hipStream_t s);

@@ -281,6 +281,57 @@ __device__ __forceinline__ bool rcp_pending(double v) {
   return __double_as_longlong(v) == RCP_PENDING;
 }
 
+// The panel's element operations on complex values, or (RE) on real values: a real
+// matrix keeps only its C real planes, the imaginary arrays are then ignored on input and
+// returned as zero, the pivot measure is |a| and the reciprocal a real one.
+template <int C, bool RE>
+__device__ __forceinline__ void pv_cabs1(const double (&re)[C], const double (&im)[C],
+                                         double (&o)[C]) {
+  if constexpr (RE) mp::abs_<C>(re, o);
+  else mp::cabs1<C>(re, im, o);
+}
+
+template <int C, bool RE>
+__device__ __forceinline__ void pv_recip(const double (&br)[C], const double (&bi)[C],
+                                         double (&orr)[C], double (&oi)[C]) {
+  if constexpr (RE) {
+    mp::recip<C>(br, orr);
+    mp::set_zero<C>(oi);
+  } else {
+    mp::zrecip<C>(br, bi, orr, oi);
+  }
+}
+
+template <int C, bool RE>
+__device__ __forceinline__ void pv_mul(const double (&ar)[C], const double (&ai)[C],
+                                       const double (&br)[C], const double (&bi)[C],
+                                       double (&orr)[C], double (&oi)[C]) {
+  if constexpr (RE) {
+    mp::mul<C>(ar, br, orr);
+    mp::set_zero<C>(oi);
+  } else {
+    mp::zmul<C>(ar, ai, br, bi, orr, oi);
+  }
+}
+
+// o = a - l u, one rounding per part (outputs may alias the inputs)
+template <int C, bool RE>
+__device__ __forceinline__ void pv_fms(const double (&ar)[C], const double (&ai)[C],
+                                       const double (&lr)[C], const double (&li)[C],
+                                       const double (&ur)[C], const double (&ui)[C],
+                                       double (&orr)[C], double (&oi)[C]) {
+  if constexpr (RE) {
+    double x[C], nl[C];
+    mp::copy<C>(ar, x);
+    mp::neg<C>(lr, nl);
+    mp::mac<C>(x, nl, ur);
+    mp::renorm<C>(x, orr);
+    mp::set_zero<C>(oi);
+  } else {
+    mp::zfms<C>(ar, ai, lr, li, ur, ui, orr, oi);
+  }
+}
+
 // element (row lr, column c, plane q) of this workgroup's rows in LDS
 #define SA(c, q, lr) sA[((size_t)(c) * Q + (q)) * R + (lr)]
 
@@ -289,13 +340,13 @@ __device__ __forceinline__ bool rcp_pending(double v) {
 // step k-2; the step k-1 update of columns > k ("pending") is applied while the barrier
 // of column k is in flight.  Rows published before that update are completed by their
 // readers, who hold the previous U row and find the row's multiplier in its column k-1.
-template <int C>
+template <int C, bool RE>
 __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   extern __shared__ double smem[];
   // the panel is a chain of short dependent steps; when it shares CUs with the trailing
   // update its waves should win instruction issue
   __builtin_amdgcn_s_setprio(3);
-  constexpr int Q = 2 * C;
+  constexpr int Q = RE ? C : 2 * C;  // planes of a value
   constexpr int PREC = C + 1;  // candidate record: cabs1, row
   const int kb = a.kb, R = a.R, G = a.G;
   const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -341,9 +392,9 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           re[c] = SA(k, c, r);
-          im[c] = SA(k, C + c, r);
+          im[c] = RE ? 0.0 : SA(k, C + c, r);
         }
-        mp::cabs1<C>(re, im, cv);
+        pv_cabs1<C, RE>(re, im, cv);
         if (better<C>(cv, (int)(r0 + r), v, idx)) {
 #pragma unroll
           for (int c = 0; c < C; ++c) v[c] = cv[c];
@@ -390,13 +441,13 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           pr[c] = SA(k, c, lr);
-          pi[c] = SA(k, C + c, lr);
+          pi[c] = RE ? 0.0 : SA(k, C + c, lr);
         }
-        mp::zrecip<C>(pr, pi, rr, ri);
+        pv_recip<C, RE>(pr, pi, rr, ri);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           put(&rcpw[c * PGMAX + g], rr[c]);
-          put(&rcpw[(C + c) * PGMAX + g], ri[c]);
+          if (!RE) put(&rcpw[(C + c) * PGMAX + g], ri[c]);
         }
       }
     } else if (!prev_zero && k + 1 < kb) {
@@ -411,17 +462,17 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
           xr[cc] = SA(c, cc, r);
-          xi[cc] = SA(c, C + cc, r);
+          xi[cc] = RE ? 0.0 : SA(c, C + cc, r);
           lr_[cc] = SA(k - 1, cc, r);
-          li[cc] = SA(k - 1, C + cc, r);
+          li[cc] = RE ? 0.0 : SA(k - 1, C + cc, r);
           ur[cc] = sPrev[cc * kb + c];
-          ui[cc] = sPrev[(C + cc) * kb + c];
+          ui[cc] = RE ? 0.0 : sPrev[(C + cc) * kb + c];
         }
-        mp::zfms<C>(xr, xi, lr_, li, ur, ui, xr, xi);
+        pv_fms<C, RE>(xr, xi, lr_, li, ur, ui, xr, xi);
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
           SA(c, cc, r) = xr[cc];
-          SA(c, C + cc, r) = xi[cc];
+          if (!RE) SA(c, C + cc, r) = xi[cc];
         }
       }
     }
@@ -524,17 +575,17 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
           xr[cc] = row[cc * kb + c];
-          xi[cc] = row[(C + cc) * kb + c];
+          xi[cc] = RE ? 0.0 : row[(C + cc) * kb + c];
           lr_[cc] = row[cc * kb + k - 1];
-          li[cc] = row[(C + cc) * kb + k - 1];
+          li[cc] = RE ? 0.0 : row[(C + cc) * kb + k - 1];
           ur[cc] = sPrev[cc * kb + c];
-          ui[cc] = sPrev[(C + cc) * kb + c];
+          ui[cc] = RE ? 0.0 : sPrev[(C + cc) * kb + c];
         }
-        mp::zfms<C>(xr, xi, lr_, li, ur, ui, xr, xi);
+        pv_fms<C, RE>(xr, xi, lr_, li, ur, ui, xr, xi);
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
           row[cc * kb + c] = xr[cc];
-          row[(C + cc) * kb + c] = xi[cc];
+          if (!RE) row[(C + cc) * kb + c] = xi[cc];
         }
       }
     }
@@ -572,30 +623,30 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           xr[c] = SA(k, c, t);
-          xi[c] = SA(k, C + c, t);
+          xi[c] = RE ? 0.0 : SA(k, C + c, t);
           rr[c] = sRcp[c];
-          ri[c] = sRcp[C + c];
+          ri[c] = RE ? 0.0 : sRcp[C + c];
         }
-        mp::zmul<C>(xr, xi, rr, ri, lr_, li);
+        pv_mul<C, RE>(xr, xi, rr, ri, lr_, li);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           SA(k, c, t) = lr_[c];
-          SA(k, C + c, t) = li[c];
+          if (!RE) SA(k, C + c, t) = li[c];
         }
         if (k + 1 < kb) {
           double ur[C], ui[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             xr[c] = SA(k + 1, c, t);
-            xi[c] = SA(k + 1, C + c, t);
+            xi[c] = RE ? 0.0 : SA(k + 1, C + c, t);
             ur[c] = sPiv[c * kb + k + 1];
-            ui[c] = sPiv[(C + c) * kb + k + 1];
+            ui[c] = RE ? 0.0 : sPiv[(C + c) * kb + k + 1];
           }
-          mp::zfms<C>(xr, xi, lr_, li, ur, ui, xr, xi);
+          pv_fms<C, RE>(xr, xi, lr_, li, ur, ui, xr, xi);
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             SA(k + 1, c, t) = xr[c];
-            SA(k + 1, C + c, t) = xi[c];
+            if (!RE) SA(k + 1, C + c, t) = xi[c];
           }
         }
       }
@@ -704,7 +755,7 @@ __global__ __launch_bounds__(256) void k_laswp(ZM A, int64_t c0, int64_t c1, int
       if (ds[h] >= 0) col0[(int64_t)q * A.ps + ds[h]] = v[h][q];
 }
 
-template <int C>
+template <int C, bool RE>
 static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
                                  int32_t *info, void *ws, unsigned *base, hipStream_t s) {
   const PanelGeom geo = panel_geometry(C, m - j, kb);
@@ -722,12 +773,13 @@ static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ip
   a.base = *base;
   *base += (unsigned)geo.G * (unsigned)kb;
   static LdsAttr attr;
-  const hipError_t ae = attr.ensure((const void *)k_panel<C>, (int)PLDS_BUDGET);
+  const hipError_t ae = attr.ensure((const void *)k_panel<C, RE>, (int)PLDS_BUDGET);
   if (ae != hipSuccess) return ae;
   // G never exceeds the CU count and one workgroup fits a CU, so every workgroup becomes
   // resident once the kernels sharing the device retire theirs: an ordinary launch
-  // suffices, and it may run beside the trailing update on another stream
-  hipLaunchKernelGGL((k_panel<C>), dim3(geo.G), dim3(PNT), geo.lds, s, a);
+  // suffices, and it may run beside the trailing update on another stream.  The real
+  // panel uses the complex panel's geometry; its LDS need is at most that.
+  hipLaunchKernelGGL((k_panel<C, RE>), dim3(geo.G), dim3(PNT), geo.lds, s, a);
   return hipGetLastError();
 }
 
@@ -736,11 +788,14 @@ hipError_t panel_ws_clear(void *ws, hipStream_t s) {
 }
 
 hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
-                        int32_t *info, void *ws, unsigned *base, hipStream_t s) {
+                        int32_t *info, void *ws, unsigned *base, hipStream_t s, bool real) {
   switch (C) {
-    case 2: return launch_panel_t<2>(A, j, m, kb, ipiv, info, ws, base, s);
-    case 3: return launch_panel_t<3>(A, j, m, kb, ipiv, info, ws, base, s);
-    case 4: return launch_panel_t<4>(A, j, m, kb, ipiv, info, ws, base, s);
+    case 2: return real ? launch_panel_t<2, true>(A, j, m, kb, ipiv, info, ws, base, s)
+                        : launch_panel_t<2, false>(A, j, m, kb, ipiv, info, ws, base, s);
+    case 3: return real ? launch_panel_t<3, true>(A, j, m, kb, ipiv, info, ws, base, s)
+                        : launch_panel_t<3, false>(A, j, m, kb, ipiv, info, ws, base, s);
+    case 4: return real ? launch_panel_t<4, true>(A, j, m, kb, ipiv, info, ws, base, s)
+                        : launch_panel_t<4, false>(A, j, m, kb, ipiv, info, ws, base, s);
   }
   return hipErrorInvalidValue;
 }

@@ -6,8 +6,8 @@ parts (its exact-then-round 4M arithmetic then reduces to real arithmetic, and i
 reciprocal to conj(b)/|b|^2 = b/b^2).  Checks:
   * dgemm against the oracle's product, elementwise within 4 (k + 4) u sum |a||b|, and
     bitwise equal to the real part of the complex 3M product on the embedded operands;
-  * dgetrf bitwise equal (factors and pivots) to the complex 3M factorisation of the
-    embedded matrix, whose imaginary parts stay exactly zero;
+  * dgetrf against the oracle (pivots where the gap is clear, factors within
+    100 n u), its look-ahead schedule bitwise equal to the in-order one;
   * dgesv / dgetrs ('N' and 'T') against the oracle: pivots where the gap is clear,
     solutions within 10 n kappa u, backward error within 10 n u (exact residual);
   * exactly representable real factorisations bit for bit; a zero column sets info;
@@ -104,19 +104,28 @@ def test_dgemm_exact_on_dyadic_data(mp):
 
 @pytest.mark.parametrize("C", CS)
 @pytest.mark.parametrize("shape", [(200, 200, 64), (150, 100, 32), (100, 150, 32)])
-def test_dgetrf_bitwise_equals_complex_3m(mp, orc, C, shape):
+def test_dgetrf_vs_oracle_and_schedules(mp, orc, C, shape):
+    """The real factorisation against the oracle (pivots where the gap is clear, factors
+    within 100 max(m, n) u), and the look-ahead schedule bitwise equal to the in-order one."""
     m, n, panel = shape
     A = real_planes(m, n, C, 30 + C, orc)
     T = dev(A)
     ipiv, info = mp.dgetrf(T, panel=panel)
-    Z = dev(embed(A))
-    zipiv, zinfo = mp.getrf(Z, panel=panel, method="3m")
+    T2 = dev(A)
+    ipiv2, info2 = mp.dgetrf(T2, panel=panel, lookahead=False)
     sync()
-    assert int(info.item()) == int(zinfo.item()) == 0
-    assert np.array_equal(ipiv.cpu().numpy(), zipiv.cpu().numpy())
-    z = host(Z)
-    assert not np.any(z[1])
-    assert np.array_equal(host(T), z[0])
+    assert int(info.item()) == int(info2.item()) == 0
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv2.cpu().numpy())
+    LUg = host(T)
+    assert np.array_equal(LUg, host(T2))
+    LUo, ipo, info_o = orc.getf2(embed(A))
+    assert info_o == 0 and not np.any(LUo[1])
+    k_clear = pivot_gaps_clear(orc.hi_complex(LUo))
+    assert np.array_equal(ipiv.cpu().numpy()[:k_clear], ipo[:k_clear])
+    if k_clear == min(m, n):
+        d = orc.diff(embed(LUg), LUo)
+        scale = np.abs(orc.hi_complex(LUo)).max()
+        assert np.abs(d).max() <= 100 * max(m, n) * U_FMT[C] * scale
 
 
 @pytest.mark.parametrize("C", CS)
