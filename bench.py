@@ -390,8 +390,8 @@ def cpu_baseline(synthgen, n, target_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
+              "runs the factorisation on one GPU", file=sys.stderr)
         sys.exit(2)
     import torch
 

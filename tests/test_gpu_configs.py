@@ -29,13 +29,16 @@ from helpers import U_FMT, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# measured figures are printed, and also appended to configs.jsonl in the directory named
+# by MPLU_TEST_RECORDS when that is set
+OUT = os.environ.get("MPLU_TEST_RECORDS")
 
 
 def record(name, **kw):
-    os.makedirs(OUT, exist_ok=True)
-    with open(os.path.join(OUT, "configs.jsonl"), "a") as f:
-        f.write(json.dumps({"test": name, **kw}) + "\n")
+    if OUT:
+        os.makedirs(OUT, exist_ok=True)
+        with open(os.path.join(OUT, "configs.jsonl"), "a") as f:
+            f.write(json.dumps({"test": name, **kw}) + "\n")
     print(name, kw)
 
 
