@@ -179,15 +179,13 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k,
  * A real multi-component matrix is C planes: plane c (component c) at
  * planes + c*plane_stride, each column-major (element (i, j) at [j*ld + i]).
  *
- * mplu_dgetrf / mplu_dgetrs / mplu_dgesv take a complex copy of their operands in the
- * workspace (imaginary planes zero).  The panels work on the real planes only (pivot
- * measure |a| in full precision, real reciprocal), the trailing updates use the real
- * product (only T1 = Re(L21) Re(U12) of Eq. 3m_cemm), and the interchanges and
- * triangular solves are the complex kernels on the copy, whose imaginary parts stay
- * zero; the results are copied back.  opts->gemm must be MPLU_GEMM_4M or MPLU_GEMM_3M
- * (both select the real product); the split methods return MPLU_E_UNSUPPORTED.
- * Argument meaning, pivots, d_info, ownership and errors are as for the complex
- * routines.
+ * mplu_dgetrf / mplu_dgetrs / mplu_dgesv run the real variants of the complex kernels on
+ * the caller's C planes: the panel (pivot measure |a| in full precision, real
+ * reciprocal), interchanges, triangular solves and substitutions, and the real product
+ * (only T1 = Re(L21) Re(U12) of Eq. 3m_cemm) for the trailing and block updates.
+ * opts->gemm must be MPLU_GEMM_4M or MPLU_GEMM_3M (both select the real product); the
+ * split methods return MPLU_E_UNSUPPORTED.  Argument meaning, pivots, d_info, ownership,
+ * errors and workspace sizes are as for the complex routines.
  */
 typedef struct {
   double *planes;
@@ -195,8 +193,7 @@ typedef struct {
   int64_t plane_stride; /* >= ld * cols; distance between planes in doubles  */
 } mplu_dmat_t;
 
-/* mplu_dgetrf_wsbytes -- workspace bytes mplu_dgetrf needs (a complex m x n copy plus
- * the complex factorisation's workspace). */
+/* mplu_dgetrf_wsbytes -- workspace bytes mplu_dgetrf needs. */
 int mplu_dgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
                         size_t *bytes);
 

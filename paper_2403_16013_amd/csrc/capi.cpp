@@ -137,9 +137,9 @@ SideStream *side_stream() {
 // the trailing update of one step restricted to columns [c0, c1): U12 := L11^-1 A12 on
 // those columns, then A22 -= L21 U12 on them
 hipError_t step_trsm(int C, ZM a, int64_t j, int jb, int64_t c0, int64_t c1, hipStream_t s,
-                     const int32_t *swl = nullptr) {
+                     const int32_t *swl, bool real) {
   if (c1 <= c0) return hipSuccess;
-  return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s, swl, 2 * jb);
+  return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s, swl, 2 * jb, real);
 }
 
 hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
@@ -154,7 +154,7 @@ hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int j
 
 hipError_t step_update(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
                        int64_t c1, void *split_ws, hipStream_t s) {
-  hipError_t e = step_trsm(C, a, j, jb, c0, c1, s);
+  hipError_t e = step_trsm(C, a, j, jb, c0, c1, s, nullptr, method == kGemmReal);
   if (e != hipSuccess) return e;
   return step_gemm(C, method, S, a, m, j, jb, c0, c1, split_ws, s);
 }
@@ -339,7 +339,7 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     for (int64_t j = 0; j < mn; j += kb) {
       const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
       HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, pws[0], &base[0], s, real));
-      HIPCHK(launch_laswp(C, a, j, j + jb, n, pws[0], jb, s));
+      HIPCHK(launch_laswp(C, a, j, j + jb, n, pws[0], jb, s, real));
       HIPCHK(step_update(C, upd, S, a, m, j, jb, j + jb, n, split_rest, s));
     }
     return 0;
@@ -370,20 +370,20 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     HIPCHK(hipStreamWaitEvent(b, sd->ev_panel, 0));
     if (nx1 > nx0) {
       // the next panel's columns: interchanges and U12 in one launch, then the product
-      HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb)));
+      HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb), real));
       HIPCHK(step_gemm(C, upd, S, a, m, j, jb, nx0, nx1, split_next, s));
     }
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device
     HIPCHK(hipEventRecord(sd->ev_chain, s));
-    HIPCHK(step_trsm(C, a, j, jb, nx1, n, b, panel_swap_list(pw, C, jb)));
+    HIPCHK(step_trsm(C, a, j, jb, nx1, n, b, panel_swap_list(pw, C, jb), real));
     HIPCHK(hipStreamWaitEvent(b, sd->ev_chain, 0));
     HIPCHK(step_gemm(C, upd, S, a, m, j, jb, nx1, n, split_rest, b));
     HIPCHK(hipEventRecord(sd->ev_rest, b));
     // panel k's interchanges on the columns left of it; the workspace holding the list is
     // next written by panel k+3, which the caller's stream starts only after the second
     // stream's step k+1 product
-    HIPCHK(launch_laswp(C, a, j, n, n, pw, jb, b));
+    HIPCHK(launch_laswp(C, a, j, n, n, pw, jb, b, real));
     if (nx1 > nx0)
       HIPCHK(launch_panel(C, a, nx0, m, (int)(nx1 - nx0), d_ipiv, d_info, pws[(k + 1) % 3],
                           &base[(k + 1) % 3], s, real));
@@ -411,9 +411,15 @@ int mplu_zgetrs_wsbytes(int prec, int64_t n, int64_t nrhs, size_t *bytes) {
   return getrs_ws(prec, n, nrhs, bytes);
 }
 
-int mplu_zgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_zmat_t LU,
-                const int32_t *d_ipiv, mplu_zmat_t B, void *d_work, size_t work_bytes,
-                void *stream) {
+}  // extern "C"
+
+namespace {
+
+// the substitutions of mplu_zgetrs; real = true: real matrices (C planes; trans 'C' is
+// then the transpose)
+int getrs_core(int prec, char trans, int64_t n, int64_t nrhs, mplu_zmat_t LU,
+               const int32_t *d_ipiv, mplu_zmat_t B, void *d_work, size_t work_bytes,
+               void *stream, bool real) {
   if (!prec_ok(prec)) return -1;
   if (trans != 'N' && trans != 'C') return -2;
   if (n < 0) return -3;
@@ -437,59 +443,70 @@ int mplu_zgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_zmat_t LU,
   if (nrhs <= kSvMaxRhs) {
     int32_t *flags = (int32_t *)((char *)wbuf + align256(sizeof(double) * 2 * C * (size_t)n * (size_t)nrhs));
     if (trans == 'N') {
-      HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, false, s));            // P b
-      HIPCHK(launch_trsv(C, true, true, false, lu, w, n, nrhs, flags, s));      // L y = P b
-      HIPCHK(launch_trsv(C, false, false, false, lu, w, n, nrhs, flags, s));    // U x = y
-      HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, true, s));
+      HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, false, s, real));            // P b
+      HIPCHK(launch_trsv(C, true, true, false, lu, w, n, nrhs, flags, s, real));      // L y = P b
+      HIPCHK(launch_trsv(C, false, false, false, lu, w, n, nrhs, flags, s, real));    // U x = y
+      HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, true, s, real));
     } else {
-      HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, false, s));
-      HIPCHK(launch_trsv(C, false, false, true, lu, w, n, nrhs, flags, s));     // U^H z = b
-      HIPCHK(launch_trsv(C, true, true, true, lu, w, n, nrhs, flags, s));       // L^H w = z
-      HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, true, s));              // x = P^T w
+      HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, false, s, real));
+      HIPCHK(launch_trsv(C, false, false, true, lu, w, n, nrhs, flags, s, real));     // U^H z = b
+      HIPCHK(launch_trsv(C, true, true, true, lu, w, n, nrhs, flags, s, real));       // L^H w = z
+      HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, true, s, real));              // x = P^T w
     }
     return 0;
   }
   const int NB = kSolveBlock;
+  const int gm = real ? 2 : 0;  // block updates: the real product, else 4M
   const int64_t nblk = (n + NB - 1) / NB;
   if (trans == 'N') {
-    HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, false, s));
+    HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, false, s, real));
     for (int64_t bi = 0; bi < nblk; ++bi) {  // L y = P b
       const int64_t i0 = bi * NB;
       const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
-      HIPCHK(launch_trsm(C, true, true, false, lu, i0, nb, w, i0, 0, nrhs, s));
+      HIPCHK(launch_trsm(C, true, true, false, lu, i0, nb, w, i0, 0, nrhs, s, nullptr, 0, real));
       if (i0 + nb < n)
-        HIPCHK(launch_gemm(C, 0, 'N', 'N', n - i0 - nb, nrhs, nb, -1, lu, i0 + nb, i0, w, i0, 0,
+        HIPCHK(launch_gemm(C, gm, 'N', 'N', n - i0 - nb, nrhs, nb, -1, lu, i0 + nb, i0, w, i0, 0,
                            1, w, i0 + nb, 0, s));
     }
     for (int64_t bi = nblk - 1; bi >= 0; --bi) {  // U x = y
       const int64_t i0 = bi * NB;
       const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
-      HIPCHK(launch_trsm(C, false, false, false, lu, i0, nb, w, i0, 0, nrhs, s));
+      HIPCHK(launch_trsm(C, false, false, false, lu, i0, nb, w, i0, 0, nrhs, s, nullptr, 0, real));
       if (i0 > 0)
-        HIPCHK(launch_gemm(C, 0, 'N', 'N', i0, nrhs, nb, -1, lu, 0, i0, w, i0, 0, 1, w, 0, 0, s));
+        HIPCHK(launch_gemm(C, gm, 'N', 'N', i0, nrhs, nb, -1, lu, 0, i0, w, i0, 0, 1, w, 0, 0, s));
     }
     // W holds x in natural order: identity copy back
-    HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, true, s));
+    HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, true, s, real));
   } else {
-    HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, false, s));
+    HIPCHK(launch_gather_rows(C, nullptr, n, nrhs, b, w, false, s, real));
     for (int64_t bi = 0; bi < nblk; ++bi) {  // U^H z = b
       const int64_t i0 = bi * NB;
       const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
-      HIPCHK(launch_trsm(C, false, false, true, lu, i0, nb, w, i0, 0, nrhs, s));
+      HIPCHK(launch_trsm(C, false, false, true, lu, i0, nb, w, i0, 0, nrhs, s, nullptr, 0, real));
       if (i0 + nb < n)
-        HIPCHK(launch_gemm(C, 0, 'C', 'N', n - i0 - nb, nrhs, nb, -1, lu, i0, i0 + nb, w, i0, 0,
+        HIPCHK(launch_gemm(C, gm, 'C', 'N', n - i0 - nb, nrhs, nb, -1, lu, i0, i0 + nb, w, i0, 0,
                            1, w, i0 + nb, 0, s));
     }
     for (int64_t bi = nblk - 1; bi >= 0; --bi) {  // L^H w = z
       const int64_t i0 = bi * NB;
       const int nb = (int)((n - i0) < NB ? (n - i0) : NB);
-      HIPCHK(launch_trsm(C, true, true, true, lu, i0, nb, w, i0, 0, nrhs, s));
+      HIPCHK(launch_trsm(C, true, true, true, lu, i0, nb, w, i0, 0, nrhs, s, nullptr, 0, real));
       if (i0 > 0)
-        HIPCHK(launch_gemm(C, 0, 'C', 'N', i0, nrhs, nb, -1, lu, i0, 0, w, i0, 0, 1, w, 0, 0, s));
+        HIPCHK(launch_gemm(C, gm, 'C', 'N', i0, nrhs, nb, -1, lu, i0, 0, w, i0, 0, 1, w, 0, 0, s));
     }
-    HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, true, s));  // x = P^T w
+    HIPCHK(launch_gather_rows(C, perm, n, nrhs, b, w, true, s, real));  // x = P^T w
   }
   return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mplu_zgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_zmat_t LU,
+                const int32_t *d_ipiv, mplu_zmat_t B, void *d_work, size_t work_bytes,
+                void *stream) {
+  return getrs_core(prec, trans, n, nrhs, LU, d_ipiv, B, d_work, work_bytes, stream, false);
 }
 
 int mplu_zgesv_wsbytes(int prec, int64_t n, int64_t nrhs, const mplu_opts_t *opts,
@@ -583,9 +600,9 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, in
 }
 
 // ------------------------------------------------------------------ real matrices
-// The Im = 0 case: a complex copy of the operands in the workspace (imaginary planes
-// zero), the complex kernels for the panels, interchanges and triangular solves, and the
-// real product for the trailing updates; the results are copied back.
+// The Im = 0 case with the same kernels in their real variants (C planes per value): the
+// panel, interchanges, triangular solves and substitutions on real values, the real
+// product for the trailing updates and block updates.
 
 static inline bool dmat_ok(const mplu_dmat_t &A, int64_t rows, int64_t cols) {
   return mat_ok(mplu_zmat_t{A.planes, A.ld, A.plane_stride}, rows, cols);
@@ -593,15 +610,9 @@ static inline bool dmat_ok(const mplu_dmat_t &A, int64_t rows, int64_t cols) {
 
 static inline ZM dm(const mplu_dmat_t &A) { return ZM{A.planes, A.ld, A.plane_stride}; }
 
-// a complex rows x cols matrix with ld = max(1, rows) carved at *off in the workspace
-static inline size_t zcopy_bytes(int C, int64_t rows, int64_t cols) {
-  const int64_t ld = rows > 1 ? rows : 1;
-  return align256(sizeof(double) * 2 * (size_t)C * (size_t)ld * (size_t)(cols > 0 ? cols : 0));
-}
-
-static inline mplu_zmat_t zcopy_at(char *base, size_t off, int64_t rows, int64_t cols) {
-  const int64_t ld = rows > 1 ? rows : 1;
-  return mplu_zmat_t{(double *)(base + off), ld, ld * (cols > 0 ? cols : 0)};
+// the descriptor as the internal routines take it (only its first C planes are touched)
+static inline mplu_zmat_t as_z(const mplu_dmat_t &A) {
+  return mplu_zmat_t{A.planes, A.ld, A.plane_stride};
 }
 
 int mplu_dgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
@@ -610,10 +621,7 @@ int mplu_dgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (!bytes) return -5;
-  size_t f = 0;
-  getrf_ws(prec, m, n, opts, &f);
-  *bytes = zcopy_bytes(prec, m, n) + f;
-  return 0;
+  return getrf_ws(prec, m, n, opts, bytes);
 }
 
 int mplu_dgetrf(int prec, int64_t m, int64_t n, mplu_dmat_t A, int32_t *d_ipiv,
@@ -623,33 +631,8 @@ int mplu_dgetrf(int prec, int64_t m, int64_t n, mplu_dmat_t A, int32_t *d_ipiv,
   if (m < 0) return -2;
   if (n < 0) return -3;
   if (!dmat_ok(A, m, n)) return -4;
-  const int64_t mn = m < n ? m : n;
-  if (mn > 0 && d_ipiv == nullptr) return -5;
-  if (d_info == nullptr) return -6;
-  // the factorisation checks the options again, but only after the copy is enqueued;
-  // check them here so that nothing is enqueued on an argument error
-  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -7;
-  const int method = gemm_method(opts);
-  if (method < 0 || method > 3) return -7;
-  if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
-  size_t need = 0;
-  mplu_dgetrf_wsbytes(prec, m, n, opts, &need);
-  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
-  if (work_bytes < need) return MPLU_E_WORKSPACE;
-  const size_t zb = zcopy_bytes(prec, m, n);
-  const mplu_zmat_t Z = zcopy_at((char *)d_work, 0, m, n);
-  hipStream_t s = (hipStream_t)stream;
-  const int kb0 = panel_width(opts);
-  for (int64_t j = 0, kb = (mn > 0 && kb0 > mn) ? mn : kb0; j < mn; j += kb) {
-    const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
-    if (panel_geometry(prec, m - j, jb).G == 0) return MPLU_E_UNSUPPORTED;
-  }
-  HIPCHK(launch_embed(prec, m, n, dm(A), zm(Z), true, s));
-  const int rc = getrf_core(prec, m, n, Z, d_ipiv, d_info, opts, (char *)d_work + zb,
-                            work_bytes - zb, stream, true);
-  if (rc != 0) return rc;
-  HIPCHK(launch_embed(prec, m, n, dm(A), zm(Z), false, s));
-  return 0;
+  return getrf_core(prec, m, n, as_z(A), d_ipiv, d_info, opts, d_work, work_bytes, stream,
+                    true);
 }
 
 int mplu_dgetrs_wsbytes(int prec, int64_t n, int64_t nrhs, size_t *bytes) {
@@ -657,10 +640,7 @@ int mplu_dgetrs_wsbytes(int prec, int64_t n, int64_t nrhs, size_t *bytes) {
   if (n < 0) return -2;
   if (nrhs < 0) return -3;
   if (!bytes) return -4;
-  size_t r = 0;
-  getrs_ws(prec, n, nrhs, &r);
-  *bytes = zcopy_bytes(prec, n, n) + zcopy_bytes(prec, n, nrhs) + r;
-  return 0;
+  return getrs_ws(prec, n, nrhs, bytes);
 }
 
 int mplu_dgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_dmat_t LU,
@@ -668,29 +648,9 @@ int mplu_dgetrs(int prec, char trans, int64_t n, int64_t nrhs, mplu_dmat_t LU,
                 void *stream) {
   if (!prec_ok(prec)) return -1;
   if (trans != 'N' && trans != 'T') return -2;
-  if (n < 0) return -3;
-  if (nrhs < 0) return -4;
-  if (!dmat_ok(LU, n, n)) return -5;
-  if (n > 0 && d_ipiv == nullptr) return -6;
-  if (!dmat_ok(B, n, nrhs)) return -7;
-  size_t need = 0;
-  mplu_dgetrs_wsbytes(prec, n, nrhs, &need);
-  if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;
-  if (work_bytes < need) return MPLU_E_WORKSPACE;
-  if (n == 0 || nrhs == 0) return 0;
-  if (n > INT32_MAX) return MPLU_E_UNSUPPORTED;
-  hipStream_t s = (hipStream_t)stream;
-  char *wb = (char *)d_work;
-  const size_t zl = zcopy_bytes(prec, n, n), zr = zcopy_bytes(prec, n, nrhs);
-  const mplu_zmat_t ZL = zcopy_at(wb, 0, n, n), ZB = zcopy_at(wb, zl, n, nrhs);
-  HIPCHK(launch_embed(prec, n, n, dm(LU), zm(ZL), true, s));
-  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), true, s));
-  // A^T = A^H when the imaginary parts are zero
-  const int rc = mplu_zgetrs(prec, trans == 'N' ? 'N' : 'C', n, nrhs, ZL, d_ipiv, ZB,
-                             wb + zl + zr, work_bytes - zl - zr, stream);
-  if (rc != 0) return rc;
-  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), false, s));
-  return 0;
+  // A^T of a real matrix is what the complex routine calls A^H
+  return getrs_core(prec, trans == 'N' ? 'N' : 'C', n, nrhs, as_z(LU), d_ipiv, as_z(B),
+                    d_work, work_bytes, stream, true);
 }
 
 int mplu_dgesv_wsbytes(int prec, int64_t n, int64_t nrhs, const mplu_opts_t *opts,
@@ -702,7 +662,7 @@ int mplu_dgesv_wsbytes(int prec, int64_t n, int64_t nrhs, const mplu_opts_t *opt
   size_t a = 0, b = 0;
   getrf_ws(prec, n, n, opts, &a);
   getrs_ws(prec, n, nrhs, &b);
-  *bytes = zcopy_bytes(prec, n, n) + zcopy_bytes(prec, n, nrhs) + (a > b ? a : b);
+  *bytes = a > b ? a : b;
   return 0;
 }
 
@@ -716,36 +676,16 @@ int mplu_dgesv(int prec, int64_t n, int64_t nrhs, mplu_dmat_t A, int32_t *d_ipiv
   if (n > 0 && d_ipiv == nullptr) return -5;
   if (!dmat_ok(B, n, nrhs)) return -6;
   if (d_info == nullptr) return -7;
-  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -8;
-  const int method = gemm_method(opts);
-  if (method < 0 || method > 3) return -8;
-  if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
   size_t need = 0;
   mplu_dgesv_wsbytes(prec, n, nrhs, opts, &need);
   if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -9;
   if (work_bytes < need) return MPLU_E_WORKSPACE;
-  const int kb0 = panel_width(opts);
-  for (int64_t j = 0, kb = (n > 0 && kb0 > n) ? n : kb0; j < n; j += kb) {
-    const int jb = (int)((n - j) < kb ? (n - j) : kb);
-    if (panel_geometry(prec, n - j, jb).G == 0) return MPLU_E_UNSUPPORTED;
-  }
-  hipStream_t s = (hipStream_t)stream;
-  char *wb = (char *)d_work;
-  const size_t za = zcopy_bytes(prec, n, n), zr = zcopy_bytes(prec, n, nrhs);
-  const mplu_zmat_t ZA = zcopy_at(wb, 0, n, n), ZB = zcopy_at(wb, za, n, nrhs);
-  HIPCHK(launch_embed(prec, n, n, dm(A), zm(ZA), true, s));
-  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), true, s));
-  int rc = getrf_core(prec, n, n, ZA, d_ipiv, d_info, opts, wb + za + zr,
-                      work_bytes - za - zr, stream, true);
+  int rc = getrf_core(prec, n, n, as_z(A), d_ipiv, d_info, opts, d_work, work_bytes, stream,
+                      true);
+  if (rc == -7) return -8;  // the options (the only argument not checked above)
   if (rc != 0) return rc;
-  if (n > 0 && nrhs > 0) {
-    rc = mplu_zgetrs(prec, 'N', n, nrhs, ZA, d_ipiv, ZB, wb + za + zr, work_bytes - za - zr,
-                     stream);
-    if (rc != 0) return rc;
-  }
-  HIPCHK(launch_embed(prec, n, n, dm(A), zm(ZA), false, s));
-  HIPCHK(launch_embed(prec, n, nrhs, dm(B), zm(ZB), false, s));
-  return 0;
+  return getrs_core(prec, 'N', n, nrhs, as_z(A), d_ipiv, as_z(B), d_work, work_bytes, stream,
+                    true);
 }
 
 int mplu_dgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k, int alpha_sign,

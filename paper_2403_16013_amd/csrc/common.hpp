@@ -101,10 +101,6 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
 // O := sa A + sb B (complex, m x n, sa and sb in {-1, 0, 1}); O may alias A or B
 hipError_t launch_zaxpby(int C, int64_t m, int64_t n, int sa, ZM A, int sb, ZM B, ZM O,
                          hipStream_t s);
-// real matrix R (C planes) <-> real planes of complex Z; to_complex also clears Z's
-// imaginary planes
-hipError_t launch_embed(int C, int64_t m, int64_t n, ZM R, ZM Z, bool to_complex,
-                        hipStream_t s);
 
 struct PanelGeom {
   int G;  // workgroups
@@ -126,23 +122,24 @@ hipError_t panel_ws_clear(void *ws, hipStream_t s);
 hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,
                         int32_t *info, void *ws, unsigned *base, hipStream_t s,
                         bool real = false);
-// apply the swap list left by launch_panel to columns [0, c0) and [c1, n)
+// apply the swap list left by launch_panel to columns [0, c0) and [c1, n) (real: C planes)
 hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
-                        int kb, hipStream_t s);
+                        int kb, hipStream_t s, bool real = false);
 
 // the interchange list a panel leaves in its workspace (see launch_panel), and the
 // interchanges applied to columns [c0, c0+ncols) of A
 const int32_t *panel_swap_list(const void *ws, int C, int kb);
 hipError_t launch_laswp_list(int C, ZM A, int64_t c0, int64_t ncols, const int32_t *swl,
-                             int swstride, hipStream_t s);
+                             int swstride, hipStream_t s, bool real = false);
 
 // op(T) X = X for an nb x nb triangle T of matrix Tm at (t0, t0), X = rows [x0, x0+nb) x
 // cols [c0, c0+ncols) of Xm.  lower: T stored lower; unit: unit diagonal; conj: op = ^H.
 // swl (optional): interchange list (as left by a panel of width swstride / 2) applied to
 // those columns of Xm first.
+// real: real matrices (C planes; conj then means transpose)
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
                        ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s,
-                       const int32_t *swl = nullptr, int swstride = 0);
+                       const int32_t *swl = nullptr, int swstride = 0, bool real = false);
 
 // Cm := beta Cm + alpha op(A) op(B);  method 0 = 4M, 1 = 3M, 2 = real (only the real
 // planes of A, B and Cm are read, only those of Cm written; 'C' acts as 'T')
@@ -164,11 +161,11 @@ hipError_t launch_gemm_split(int C, bool i8, int S, char opA, char opB, int64_t 
 // flags: trsv_flag_words(n, nrhs) int32 of workspace (cleared by the launcher)
 int64_t trsv_flag_words(int64_t n, int64_t nrhs);
 hipError_t launch_trsv(int C, bool lower, bool unit, bool conj, ZM Tm, ZM Xm, int64_t n,
-                       int64_t nrhs, int32_t *flags, hipStream_t s);
+                       int64_t nrhs, int32_t *flags, hipStream_t s, bool real = false);
 
 // getrs helpers: perm from ipiv (n entries), then gather / scatter rows of B
 hipError_t launch_perm(const int32_t *ipiv, int64_t n, int32_t *perm, hipStream_t s);
 hipError_t launch_gather_rows(int C, const int32_t *perm, int64_t n, int64_t nrhs, ZM B, ZM W,
-                              bool scatter, hipStream_t s);
+                              bool scatter, hipStream_t s, bool real = false);
 
 }  // namespace mplu

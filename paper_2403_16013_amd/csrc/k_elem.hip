@@ -84,11 +84,11 @@ __global__ __launch_bounds__(1024) void k_perm(const int32_t *ipiv, int64_t n, i
   if (r < n) perm[pos] = (int32_t)r;
 }
 
-// gather: W[k, :] = B[perm[k], :];  scatter: B[perm[k], :] = W[k, :]
-template <int C>
+// gather: W[k, :] = B[perm[k], :];  scatter: B[perm[k], :] = W[k, :]  (over `planes`
+// planes: 2C for complex, C for real matrices)
 __global__ __launch_bounds__(256) void k_gather(const int32_t *perm, int64_t n, int64_t nrhs,
-                                                ZM B, ZM W, int scatter) {
-  const int64_t total = n * nrhs * 2 * C;
+                                                ZM B, ZM W, int scatter, int planes) {
+  const int64_t total = n * nrhs * planes;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = e % n;
@@ -100,21 +100,6 @@ __global__ __launch_bounds__(256) void k_gather(const int32_t *perm, int64_t n, 
     double *wp = W.p + q * W.ps + r * W.ld + k;
     if (scatter) *bp = *wp;
     else *wp = *bp;
-  }
-}
-
-// Real matrices on the complex kernels (the Im = 0 case): to = 1 copies the C real planes
-// of R into the real planes of Z and clears Z's imaginary planes; to = 0 copies the real
-// planes of Z back into R.
-__global__ __launch_bounds__(256) void k_embed(int64_t m, int64_t n, int C, ZM R, ZM Z, int to) {
-  const int64_t planes = to ? 2 * C : C;
-  const int64_t total = m * n * planes;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % m, rest = e / m, j = rest % n, q = rest / n;
-    double *zp = Z.p + q * Z.ps + j * Z.ld + i;
-    if (!to) R.p[q * R.ps + j * R.ld + i] = *zp;
-    else *zp = (q < C) ? R.p[q * R.ps + j * R.ld + i] : 0.0;
   }
 }
 
@@ -184,14 +169,6 @@ hipError_t launch_convert(int Cs, int Cd, int64_t m, int64_t n, ZM A, ZM B, hipS
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_embed(int C, int64_t m, int64_t n, ZM R, ZM Z, bool to_complex,
-                        hipStream_t s) {
-  if (m <= 0 || n <= 0) return hipSuccess;
-  const int g = grid_for(m * n * (to_complex ? 2 * C : C), 256);
-  hipLaunchKernelGGL(k_embed, dim3(g), dim3(256), 0, s, m, n, C, R, Z, (int)to_complex);
-  return hipGetLastError();
-}
-
 hipError_t launch_zaxpby(int C, int64_t m, int64_t n, int sa, ZM A, int sb, ZM B, ZM O,
                          hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
@@ -218,15 +195,13 @@ hipError_t launch_perm(const int32_t *ipiv, int64_t n, int32_t *perm, hipStream_
 }
 
 hipError_t launch_gather_rows(int C, const int32_t *perm, int64_t n, int64_t nrhs, ZM B, ZM W,
-                              bool scatter, hipStream_t s) {
+                              bool scatter, hipStream_t s, bool real) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
-  const int g = grid_for(n * nrhs * 2 * C, 256);
-  switch (C) {
-    case 2: hipLaunchKernelGGL(k_gather<2>, dim3(g), dim3(256), 0, s, perm, n, nrhs, B, W, (int)scatter); break;
-    case 3: hipLaunchKernelGGL(k_gather<3>, dim3(g), dim3(256), 0, s, perm, n, nrhs, B, W, (int)scatter); break;
-    case 4: hipLaunchKernelGGL(k_gather<4>, dim3(g), dim3(256), 0, s, perm, n, nrhs, B, W, (int)scatter); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (C < 2 || C > 4) return hipErrorInvalidValue;
+  const int planes = real ? C : 2 * C;
+  const int g = grid_for(n * nrhs * planes, 256);
+  hipLaunchKernelGGL(k_gather, dim3(g), dim3(256), 0, s, perm, n, nrhs, B, W, (int)scatter,
+                     planes);
   return hipGetLastError();
 }
 

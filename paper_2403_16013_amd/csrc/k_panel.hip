@@ -716,7 +716,8 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
 }
 #undef SA
 
-template <int C>
+// RE: a real matrix, C planes
+template <int C, bool RE>
 __global__ __launch_bounds__(256) void k_laswp(ZM A, int64_t c0, int64_t c1, int64_t n,
                                                const int32_t *swl, int kb) {
   const int cnt = swl[0];
@@ -726,7 +727,7 @@ __global__ __launch_bounds__(256) void k_laswp(ZM A, int64_t c0, int64_t c1, int
   const int64_t ncols = c0 + (n - c1);
   if (w >= ncols) return;
   const int64_t col = w < c0 ? w : c1 + (w - c0);
-  constexpr int Q = 2 * C;
+  constexpr int Q = RE ? C : 2 * C;
   // every read before any write, so the loads of all planes are in flight together; the
   // list (2 kb slots per half) is read in the same round trip as its count
   double *col0 = A.p + col * A.ld;
@@ -804,33 +805,33 @@ const int32_t *panel_swap_list(const void *ws, int C, int kb) {
   return carve(const_cast<void *>(ws), C, kb, nullptr).swl;
 }
 
-hipError_t launch_laswp_list(int C, ZM A, int64_t c0, int64_t ncols, const int32_t *swl,
-                             int swstride, hipStream_t s) {
+// columns [0, c0) and [c1, n) of A (one wave per column, four per workgroup)
+static hipError_t go_laswp(int C, bool real, ZM A, int64_t c0, int64_t c1, int64_t n,
+                           const int32_t *swl, int kb, hipStream_t s) {
+  const int64_t ncols = c0 + (n - c1);
   if (ncols <= 0) return hipSuccess;
-  const int64_t blocks = (ncols + 3) / 4;
-  const int kb = swstride / 2;
+  const dim3 grid((unsigned)((ncols + 3) / 4));
+#define LASWP(CC, RR) hipLaunchKernelGGL((k_laswp<CC, RR>), grid, dim3(256), 0, s, A, c0, c1, n, swl, kb)
   switch (C) {
-    case 2: hipLaunchKernelGGL(k_laswp<2>, dim3((unsigned)blocks), dim3(256), 0, s, A, (int64_t)0, c0, c0 + ncols, swl, kb); break;
-    case 3: hipLaunchKernelGGL(k_laswp<3>, dim3((unsigned)blocks), dim3(256), 0, s, A, (int64_t)0, c0, c0 + ncols, swl, kb); break;
-    case 4: hipLaunchKernelGGL(k_laswp<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, (int64_t)0, c0, c0 + ncols, swl, kb); break;
+    case 2: if (real) LASWP(2, true); else LASWP(2, false); break;
+    case 3: if (real) LASWP(3, true); else LASWP(3, false); break;
+    case 4: if (real) LASWP(4, true); else LASWP(4, false); break;
     default: return hipErrorInvalidValue;
   }
+#undef LASWP
   return hipGetLastError();
 }
 
-hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
-                        int kb, hipStream_t s) {
-  const int64_t ncols = c0 + (n - c1);
+hipError_t launch_laswp_list(int C, ZM A, int64_t c0, int64_t ncols, const int32_t *swl,
+                             int swstride, hipStream_t s, bool real) {
   if (ncols <= 0) return hipSuccess;
+  return go_laswp(C, real, A, 0, c0, c0 + ncols, swl, swstride / 2, s);
+}
+
+hipError_t launch_laswp(int C, ZM A, int64_t c0, int64_t c1, int64_t n, const void *ws,
+                        int kb, hipStream_t s, bool real) {
   PanelWS w = carve(const_cast<void *>(ws), C, kb, nullptr);
-  const int64_t blocks = (ncols + 3) / 4;
-  switch (C) {
-    case 2: hipLaunchKernelGGL(k_laswp<2>, dim3((unsigned)blocks), dim3(256), 0, s, A, c0, c1, n, w.swl, kb); break;
-    case 3: hipLaunchKernelGGL(k_laswp<3>, dim3((unsigned)blocks), dim3(256), 0, s, A, c0, c1, n, w.swl, kb); break;
-    case 4: hipLaunchKernelGGL(k_laswp<4>, dim3((unsigned)blocks), dim3(256), 0, s, A, c0, c1, n, w.swl, kb); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return go_laswp(C, real, A, c0, c1, n, w.swl, kb, s);
 }
 
 }  // namespace mplu

@@ -25,11 +25,16 @@ struct TrsmArgs {
   int swstride;
 };
 
-// op(T)[r][i]
-template <int C, bool CONJ>
+// op(T)[r][i]; RE: a real matrix (C planes), op = transpose when CONJ, im returned zero
+template <int C, bool CONJ, bool RE>
 __device__ __forceinline__ void ld_opT(const TrsmArgs &a, int r, int i, double (&re)[C],
                                        double (&im)[C]) {
-  if (CONJ) {
+  if (RE) {
+    if (CONJ) ld_re<C>(a.T, a.t0 + i, a.t0 + r, re);
+    else ld_re<C>(a.T, a.t0 + r, a.t0 + i, re);
+#pragma unroll
+    for (int c = 0; c < C; ++c) im[c] = 0.0;
+  } else if (CONJ) {
     ld_z<C>(a.T, a.t0 + i, a.t0 + r, re, im);
 #pragma unroll
     for (int c = 0; c < C; ++c) im[c] = -im[c];
@@ -52,10 +57,11 @@ __device__ __forceinline__ double wbcast(double v, int s) {
 // reciprocals of the diagonal.  Each wave then owns TW right-hand-side columns at a
 // time, one row per lane: a step finishes unknown s on lane s, broadcasts it across the
 // wave and updates the other rows, with no workgroup barrier inside the sweep.
-template <int C, bool LOWER, bool UNIT, bool CONJ, int TW>
+// RE: real matrices (only the C real planes are read and written), real arithmetic.
+template <int C, bool LOWER, bool UNIT, bool CONJ, int TW, bool RE>
 __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   extern __shared__ double smem[];
-  constexpr int Q = 2 * C;
+  constexpr int Q = RE ? C : 2 * C;
   // TW: columns per wave in flight (more hides latency, fewer spreads a narrow strip)
   const int nb = a.nb, NBC = a.nbc, t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int ntri = nb * (nb - 1) / 2;
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
       const bool in = i < nb && (LOWER ? (lane > i && lane < nb) : (lane < i));
       double tr[C], ti[C];
       if (in) {
-        ld_opT<C, CONJ>(a, lane, i, tr, ti);
+        ld_opT<C, CONJ, RE>(a, lane, i, tr, ti);
       } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) tr[c] = ti[c] = 0.0;
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         tv[u][c] = tr[c];
-        tv[u][C + c] = ti[c];
+        if (!RE) tv[u][RE ? 0 : C + c] = ti[c];
       }
     }
 #pragma unroll
@@ -139,12 +145,13 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   if (!UNIT) {
     for (int i = t; i < nb; i += 256) {
       double dr[C], di[C], rr[C], ri[C];
-      ld_opT<C, CONJ>(a, i, i, dr, di);
-      mp::zrecip<C>(dr, di, rr, ri);
+      ld_opT<C, CONJ, RE>(a, i, i, dr, di);
+      if (RE) mp::recip<C>(dr, rr);
+      else mp::zrecip<C>(dr, di, rr, ri);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         sR[c * nb + i] = rr[c];
-        sR[(C + c) * nb + i] = ri[c];
+        if (!RE) sR[(C + c) * nb + i] = ri[c];
       }
     }
   }
@@ -154,14 +161,18 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     rr[c] = (!UNIT && lane < nb) ? sR[c * nb + lane] : 0.0;
-    ri[c] = (!UNIT && lane < nb) ? sR[(C + c) * nb + lane] : 0.0;
+    ri[c] = (!RE && !UNIT && lane < nb) ? sR[(C + c) * nb + lane] : 0.0;
   }
 
   for (int cc0 = w * TW; cc0 < ncl; cc0 += 4 * TW) {
     double xr[TW][C], xi[TW][C];
 #pragma unroll
     for (int h = 0; h < TW; ++h) {
-      if (lane < nb && cc0 + h < ncl) {
+      if (RE && lane < nb && cc0 + h < ncl) {
+        ld_re<C>(a.X, a.x0 + lane, cb + cc0 + h, xr[h]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) xi[h][c] = 0.0;
+      } else if (lane < nb && cc0 + h < ncl) {
         ld_z<C>(a.X, a.x0 + lane, cb + cc0 + h, xr[h], xi[h]);
       } else {
 #pragma unroll
@@ -174,7 +185,12 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
 #pragma unroll
         for (int h = 0; h < TW; ++h) {
           double orr[C], oi[C];
-          mp::zmul<C>(xr[h], xi[h], rr, ri, orr, oi);
+          if (RE) {
+            mp::mul<C>(xr[h], rr, orr);
+            mp::set_zero<C>(oi);
+          } else {
+            mp::zmul<C>(xr[h], xi[h], rr, ri, orr, oi);
+          }
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             xr[h][c] = orr[c];
@@ -188,7 +204,7 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         tr[c] = upd ? sT[(size_t)c * ntri + off] : 0.0;
-        ti[c] = upd ? sT[(size_t)(C + c) * ntri + off] : 0.0;
+        ti[c] = (!RE && upd) ? sT[(size_t)(RE ? 0 : C + c) * ntri + off] : 0.0;
       }
 #pragma unroll
       for (int h = 0; h < TW; ++h) {
@@ -196,55 +212,69 @@ __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           yr[c] = wbcast(xr[h][c], i);
-          yi[c] = wbcast(xi[h][c], i);
+          yi[c] = RE ? 0.0 : wbcast(xi[h][c], i);
         }
-        if (upd) mp::zfms<C>(xr[h], xi[h], tr, ti, yr, yi, xr[h], xi[h]);
+        if (upd) {
+          if (RE) {  // x -= t y
+            double l[C], nt[C];
+            mp::copy<C>(xr[h], l);
+            mp::neg<C>(tr, nt);
+            mp::mac<C>(l, nt, yr);
+            mp::renorm<C>(l, xr[h]);
+          } else {
+            mp::zfms<C>(xr[h], xi[h], tr, ti, yr, yi, xr[h], xi[h]);
+          }
+        }
       }
     }
 #pragma unroll
     for (int h = 0; h < TW; ++h)
-      if (lane < nb && cc0 + h < ncl) st_z<C>(a.X, a.x0 + lane, cb + cc0 + h, xr[h], xi[h]);
+      if (lane < nb && cc0 + h < ncl) {
+        if (RE) st_re<C>(a.X, a.x0 + lane, cb + cc0 + h, xr[h]);
+        else st_z<C>(a.X, a.x0 + lane, cb + cc0 + h, xr[h], xi[h]);
+      }
   }
 }
 
-template <int C, bool LOWER, bool UNIT, bool CONJ, int TW>
+template <int C, bool LOWER, bool UNIT, bool CONJ, int TW, bool RE>
 static hipError_t go_tw(const TrsmArgs &a, hipStream_t s) {
-  constexpr int Q = 2 * C;
+  constexpr int Q = RE ? C : 2 * C;
   const size_t lds = sizeof(double) * ((size_t)a.nb * Q + (size_t)Q * (a.nb * (a.nb - 1) / 2));
   static LdsAttr attr;
-  const hipError_t e = attr.ensure((const void *)k_trsm<C, LOWER, UNIT, CONJ, TW>, 160 * 1024);
+  const hipError_t e = attr.ensure((const void *)k_trsm<C, LOWER, UNIT, CONJ, TW, RE>, 160 * 1024);
   if (e != hipSuccess) return e;
   const int64_t blocks = (a.ncols + a.nbc - 1) / a.nbc;
-  hipLaunchKernelGGL((k_trsm<C, LOWER, UNIT, CONJ, TW>), dim3((unsigned)blocks), dim3(256), lds,
-                     s, a);
+  hipLaunchKernelGGL((k_trsm<C, LOWER, UNIT, CONJ, TW, RE>), dim3((unsigned)blocks), dim3(256),
+                     lds, s, a);
   return hipGetLastError();
 }
 
 // a strip of 4 columns per workgroup runs one column per wave
-template <int C, bool LOWER, bool UNIT, bool CONJ>
+template <int C, bool LOWER, bool UNIT, bool CONJ, bool RE>
 static hipError_t go(const TrsmArgs &a, hipStream_t s) {
-  return a.nbc == 4 ? go_tw<C, LOWER, UNIT, CONJ, 1>(a, s) : go_tw<C, LOWER, UNIT, CONJ, 2>(a, s);
+  return a.nbc == 4 ? go_tw<C, LOWER, UNIT, CONJ, 1, RE>(a, s)
+                    : go_tw<C, LOWER, UNIT, CONJ, 2, RE>(a, s);
 }
 
-template <int C>
+template <int C, bool RE>
 static hipError_t dispatch(bool lower, bool unit, bool conj, const TrsmArgs &a, hipStream_t s) {
   // op(T) is lower when T is lower and not transposed, or T upper and transposed
   const bool opl = lower != conj;
   if (opl) {
-    if (unit) return conj ? go<C, true, true, true>(a, s) : go<C, true, true, false>(a, s);
-    return conj ? go<C, true, false, true>(a, s) : go<C, true, false, false>(a, s);
+    if (unit) return conj ? go<C, true, true, true, RE>(a, s) : go<C, true, true, false, RE>(a, s);
+    return conj ? go<C, true, false, true, RE>(a, s) : go<C, true, false, false, RE>(a, s);
   }
-  if (unit) return conj ? go<C, false, true, true>(a, s) : go<C, false, true, false>(a, s);
-  return conj ? go<C, false, false, true>(a, s) : go<C, false, false, false>(a, s);
+  if (unit) return conj ? go<C, false, true, true, RE>(a, s) : go<C, false, true, false, RE>(a, s);
+  return conj ? go<C, false, false, true, RE>(a, s) : go<C, false, false, false, RE>(a, s);
 }
 
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
                        ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s,
-                       const int32_t *swl, int swstride) {
+                       const int32_t *swl, int swstride, bool real) {
   if (nb <= 0 || ncols <= 0) return hipSuccess;
   if (nb > 64) {
     if (swl) {
-      hipError_t e = launch_laswp_list(C, Xm, c0, ncols, swl, swstride, s);
+      hipError_t e = launch_laswp_list(C, Xm, c0, ncols, swl, swstride, s, real);
       if (e != hipSuccess) return e;
     }
     // one row per lane: split op(T) into halves,
@@ -254,20 +284,26 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
     const bool opl = lower != conj;
     const char opA = conj ? 'C' : 'N';
     hipError_t e;
+    const int gm = real ? 2 : 0;  // the real product, else 4M
     if (opl) {
-      if ((e = launch_trsm(C, lower, unit, conj, Tm, t0, h, Xm, x0, c0, ncols, s)) != hipSuccess) return e;
+      if ((e = launch_trsm(C, lower, unit, conj, Tm, t0, h, Xm, x0, c0, ncols, s, nullptr, 0,
+                           real)) != hipSuccess)
+        return e;
       // T21 = op(T)[h:, :h]: stored at (t0+h, t0) untransposed, else (t0, t0+h) transposed
-      if ((e = launch_gemm(C, 0, opA, 'N', r, ncols, h, -1, Tm, conj ? t0 : t0 + h,
+      if ((e = launch_gemm(C, gm, opA, 'N', r, ncols, h, -1, Tm, conj ? t0 : t0 + h,
                            conj ? t0 + h : t0, Xm, x0, c0, 1, Xm, x0 + h, c0, s)) != hipSuccess)
         return e;
-      return launch_trsm(C, lower, unit, conj, Tm, t0 + h, r, Xm, x0 + h, c0, ncols, s);
+      return launch_trsm(C, lower, unit, conj, Tm, t0 + h, r, Xm, x0 + h, c0, ncols, s, nullptr,
+                         0, real);
     }
-    if ((e = launch_trsm(C, lower, unit, conj, Tm, t0 + h, r, Xm, x0 + h, c0, ncols, s)) != hipSuccess) return e;
+    if ((e = launch_trsm(C, lower, unit, conj, Tm, t0 + h, r, Xm, x0 + h, c0, ncols, s, nullptr,
+                         0, real)) != hipSuccess)
+      return e;
     // T12 = op(T)[:h, h:]: stored at (t0, t0+h) untransposed, else (t0+h, t0) transposed
-    if ((e = launch_gemm(C, 0, opA, 'N', h, ncols, r, -1, Tm, conj ? t0 + h : t0,
+    if ((e = launch_gemm(C, gm, opA, 'N', h, ncols, r, -1, Tm, conj ? t0 + h : t0,
                          conj ? t0 : t0 + h, Xm, x0 + h, c0, 1, Xm, x0, c0, s)) != hipSuccess)
       return e;
-    return launch_trsm(C, lower, unit, conj, Tm, t0, h, Xm, x0, c0, ncols, s);
+    return launch_trsm(C, lower, unit, conj, Tm, t0, h, Xm, x0, c0, ncols, s, nullptr, 0, real);
   }
   TrsmArgs a;
   a.T = Tm;
@@ -287,9 +323,9 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
   a.nbc = (int)(nbc < 8 ? 8 : nbc);
   if (a.ncols <= 256) a.nbc = 4;
   switch (C) {
-    case 2: return dispatch<2>(lower, unit, conj, a, s);
-    case 3: return dispatch<3>(lower, unit, conj, a, s);
-    case 4: return dispatch<4>(lower, unit, conj, a, s);
+    case 2: return real ? dispatch<2, true>(lower, unit, conj, a, s) : dispatch<2, false>(lower, unit, conj, a, s);
+    case 3: return real ? dispatch<3, true>(lower, unit, conj, a, s) : dispatch<3, false>(lower, unit, conj, a, s);
+    case 4: return real ? dispatch<4, true>(lower, unit, conj, a, s) : dispatch<4, false>(lower, unit, conj, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -34,11 +34,16 @@ struct SvArgs {
   int32_t *flags;  // [nblk * ngrp] ready words, then one sticky expiry word
 };
 
-// op(T)[r][c]
-template <int C, bool CONJ>
+// op(T)[r][c]; RE: a real matrix (C planes), op = transpose when CONJ, im returned zero
+template <int C, bool CONJ, bool RE>
 __device__ __forceinline__ void ld_op(const ZM &T, int64_t r, int64_t c, double (&re)[C],
                                       double (&im)[C]) {
-  if (CONJ) {
+  if (RE) {
+    if (CONJ) ld_re<C>(T, c, r, re);
+    else ld_re<C>(T, r, c, re);
+#pragma unroll
+    for (int k = 0; k < C; ++k) im[k] = 0.0;
+  } else if (CONJ) {
     ld_z<C>(T, c, r, re, im);
 #pragma unroll
     for (int k = 0; k < C; ++k) im[k] = -im[k];
@@ -64,9 +69,11 @@ __device__ __forceinline__ double bcast(double v, int s) {
 
 // LOWER: op(T) lower triangular (forward sweep), else upper (backward sweep);
 // UNIT: unit diagonal; CONJ: op(T) = T^H; NR: right-hand sides per group.
-template <int C, bool LOWER, bool UNIT, bool CONJ, int NR>
+// RE: real matrices (only the C real planes are read and written), real arithmetic.
+template <int C, bool LOWER, bool UNIT, bool CONJ, int NR, bool RE>
 __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
-  constexpr int Q = 2 * C;
+  constexpr int Q = RE ? C : 2 * C;
+  constexpr int CI = RE ? 0 : C;  // plane offset of the imaginary part (unused when RE)
   extern __shared__ double smem[];
   double *sx = smem;                          // [Q][NR][SVB]   published block being folded
   double *sp = sx + Q * NR * SVB;             // [4][Q][NR][SVB] per-wave partial sums
@@ -97,16 +104,21 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
       const int u = c * SVCH + uu;
       double re[C], im[C];
       if (row < nr && u < nr) {
-        ld_op<C, CONJ>(T, r0 + row, r0 + col_of(u), re, im);
+        ld_op<C, CONJ, RE>(T, r0 + row, r0 + col_of(u), re, im);
         if (!UNIT) {
           // row `row` of the block divided by its diagonal entry (by its reciprocal)
           double rr[C], ri[C], orr[C], oi[C];
 #pragma unroll
           for (int k = 0; k < C; ++k) {
             rr[k] = sRc[k * SVB + row];
-            ri[k] = sRc[(C + k) * SVB + row];
+            ri[k] = RE ? 0.0 : sRc[(CI + k) * SVB + row];
           }
-          mp::zmul<C>(re, im, rr, ri, orr, oi);
+          if (RE) {
+            mp::mul<C>(re, rr, orr);
+            mp::set_zero<C>(oi);
+          } else {
+            mp::zmul<C>(re, im, rr, ri, orr, oi);
+          }
 #pragma unroll
           for (int k = 0; k < C; ++k) {
             re[k] = orr[k];
@@ -120,7 +132,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
       for (int k = 0; k < C; ++k) {
         dst[((size_t)k * SVCH + uu) * SVB + row] = re[k];
-        dst[((size_t)(C + k) * SVCH + uu) * SVB + row] = im[k];
+        if (!RE) dst[((size_t)(CI + k) * SVCH + uu) * SVB + row] = im[k];
       }
     }
   };
@@ -132,12 +144,13 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
   if (!UNIT) {
     if (w == 0 && lane < nr) {
       double dr[C], di[C], rr[C], ri[C];
-      ld_op<C, CONJ>(T, r0 + lane, r0 + lane, dr, di);
-      mp::zrecip<C>(dr, di, rr, ri);
+      ld_op<C, CONJ, RE>(T, r0 + lane, r0 + lane, dr, di);
+      if (RE) mp::recip<C>(dr, rr);
+      else mp::zrecip<C>(dr, di, rr, ri);
 #pragma unroll
       for (int k = 0; k < C; ++k) {
         sRc[k * SVB + lane] = rr[k];
-        sRc[(C + k) * SVB + lane] = ri[k];
+        if (!RE) sRc[(CI + k) * SVB + lane] = ri[k];
       }
     }
     __syncthreads();
@@ -169,7 +182,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
         const int col = cbeg + half * TB + u;
         double tr[C], ti[C];
         if (lane < nr && col < nj) {
-          ld_op<C, CONJ>(T, r0 + lane, j0 + col, tr, ti);
+          ld_op<C, CONJ, RE>(T, r0 + lane, j0 + col, tr, ti);
         } else {
 #pragma unroll
           for (int k = 0; k < C; ++k) tr[k] = ti[k] = 0.0;
@@ -177,7 +190,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
           tv[u][k] = tr[k];
-          tv[u][C + k] = ti[k];
+          if (!RE) tv[u][CI + k] = ti[k];
         }
       }
       if (half == 0) {
@@ -220,7 +233,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
             for (int k = 0; k < C; ++k) {
               tr[k] = tv[u][k];
-              ti[k] = tv[u][C + k];
+              ti[k] = RE ? 0.0 : tv[u][CI + k];
               ntr[k] = -tr[k];
               nti[k] = -ti[k];
             }
@@ -230,13 +243,15 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
               for (int k = 0; k < C; ++k) {
                 xr[k] = sx[((size_t)k * NR + h) * SVB + col];
-                xi[k] = sx[((size_t)(C + k) * NR + h) * SVB + col];
+                xi[k] = RE ? 0.0 : sx[((size_t)(CI + k) * NR + h) * SVB + col];
               }
               // acc -= t x
               mp::mac<C>(accR[h], ntr, xr);
-              mp::mac<C>(accR[h], ti, xi);
-              mp::mac<C>(accI[h], ntr, xi);
-              mp::mac<C>(accI[h], nti, xr);
+              if (!RE) {
+                mp::mac<C>(accR[h], ti, xi);
+                mp::mac<C>(accI[h], ntr, xi);
+                mp::mac<C>(accI[h], nti, xr);
+              }
             }
           }
         }
@@ -269,7 +284,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       sp[(((size_t)w * Q + k) * NR + h) * SVB + lane] = pr[k];
-      sp[(((size_t)w * Q + C + k) * NR + h) * SVB + lane] = pi[k];
+      if (!RE) sp[(((size_t)w * Q + CI + k) * NR + h) * SVB + lane] = pi[k];
     }
   }
   __syncthreads();
@@ -279,7 +294,11 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
     for (int h = 0; h < NR; ++h) {
       double lr[C], li[C];
-      if (lane < nr && h < ncr) {
+      if (RE && lane < nr && h < ncr) {
+        ld_re<C>(X, r0 + lane, x0 + h, lr);
+#pragma unroll
+        for (int k = 0; k < C; ++k) li[k] = 0.0;
+      } else if (lane < nr && h < ncr) {
         ld_z<C>(X, r0 + lane, x0 + h, lr, li);
       } else {
 #pragma unroll
@@ -291,10 +310,10 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
           vr[k] = sp[(((size_t)ww * Q + k) * NR + h) * SVB + lane];
-          vi[k] = sp[(((size_t)ww * Q + C + k) * NR + h) * SVB + lane];
+          vi[k] = RE ? 0.0 : sp[(((size_t)ww * Q + CI + k) * NR + h) * SVB + lane];
         }
         mp::push_mp<C>(lr, vr);
-        mp::push_mp<C>(li, vi);
+        if (!RE) mp::push_mp<C>(li, vi);
       }
       mp::renorm<C>(lr, yr[h]);
       mp::renorm<C>(li, yi[h]);
@@ -303,9 +322,14 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
           rr[k] = sRc[k * SVB + lane];
-          ri[k] = sRc[(C + k) * SVB + lane];
+          ri[k] = RE ? 0.0 : sRc[(CI + k) * SVB + lane];
         }
-        mp::zmul<C>(yr[h], yi[h], rr, ri, orr, oi);
+        if (RE) {
+          mp::mul<C>(yr[h], rr, orr);
+          mp::set_zero<C>(oi);
+        } else {
+          mp::zmul<C>(yr[h], yi[h], rr, ri, orr, oi);
+        }
 #pragma unroll
         for (int k = 0; k < C; ++k) {
           yr[h][k] = orr[k];
@@ -326,7 +350,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
         for (int k = 0; k < C; ++k) {
           tr[k] = ch[((size_t)k * SVCH + uu) * SVB + lane];
-          ti[k] = ch[((size_t)(C + k) * SVCH + uu) * SVB + lane];
+          ti[k] = RE ? 0.0 : ch[((size_t)(CI + k) * SVCH + uu) * SVB + lane];
         }
         const bool upd = lane < nr && (LOWER ? lane > s : lane < s);
 #pragma unroll
@@ -335,9 +359,19 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
           for (int k = 0; k < C; ++k) {
             xr[k] = bcast(yr[h][k], s);
-            xi[k] = bcast(yi[h][k], s);
+            xi[k] = RE ? 0.0 : bcast(yi[h][k], s);
           }
-          if (upd) mp::zfms<C>(yr[h], yi[h], tr, ti, xr, xi, yr[h], yi[h]);
+          if (upd) {
+            if (RE) {  // y -= t x
+              double l[C], nt[C];
+              mp::copy<C>(yr[h], l);
+              mp::neg<C>(tr, nt);
+              mp::mac<C>(l, nt, xr);
+              mp::renorm<C>(l, yr[h]);
+            } else {
+              mp::zfms<C>(yr[h], yi[h], tr, ti, xr, xi, yr[h], yi[h]);
+            }
+          }
         }
       }
     } else if (c + 1 < nchunk) {
@@ -357,7 +391,7 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
 #pragma unroll
           for (int k = 0; k < C; ++k) {
             sv_put(b + (int64_t)k * X.ps, bad ? __builtin_nan("") : yr[h][k]);
-            sv_put(b + (int64_t)(C + k) * X.ps, bad ? __builtin_nan("") : yi[h][k]);
+            if (!RE) sv_put(b + (int64_t)(C + k) * X.ps, bad ? __builtin_nan("") : yi[h][k]);
           }
         }
       }
@@ -369,29 +403,29 @@ __global__ __launch_bounds__(256) void k_trsv(SvArgs a) {
   }
 }
 
-template <int C, bool LOWER, bool UNIT, bool CONJ, int NR>
+template <int C, bool LOWER, bool UNIT, bool CONJ, int NR, bool RE>
 static hipError_t go_sv(const SvArgs &a, hipStream_t s) {
-  constexpr int Q = 2 * C;
+  constexpr int Q = RE ? C : 2 * C;
   const size_t lds =
       sizeof(double) * ((size_t)5 * Q * NR * SVB + (size_t)2 * Q * SVCH * SVB + (size_t)Q * SVB);
   static LdsAttr attr;
-  const hipError_t e = attr.ensure((const void *)k_trsv<C, LOWER, UNIT, CONJ, NR>, (int)lds);
+  const hipError_t e = attr.ensure((const void *)k_trsv<C, LOWER, UNIT, CONJ, NR, RE>, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_trsv<C, LOWER, UNIT, CONJ, NR>), dim3((unsigned)(a.nblk * a.ngrp)),
+  hipLaunchKernelGGL((k_trsv<C, LOWER, UNIT, CONJ, NR, RE>), dim3((unsigned)(a.nblk * a.ngrp)),
                      dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
-template <int C, int NR>
+template <int C, int NR, bool RE>
 static hipError_t dispatch_sv(bool lower, bool unit, bool conj, const SvArgs &a, hipStream_t s) {
   // op(T) is lower when T is lower and not transposed, or T upper and transposed
   const bool opl = lower != conj;
   if (opl) {
-    if (unit) return conj ? go_sv<C, true, true, true, NR>(a, s) : go_sv<C, true, true, false, NR>(a, s);
-    return conj ? go_sv<C, true, false, true, NR>(a, s) : go_sv<C, true, false, false, NR>(a, s);
+    if (unit) return conj ? go_sv<C, true, true, true, NR, RE>(a, s) : go_sv<C, true, true, false, NR, RE>(a, s);
+    return conj ? go_sv<C, true, false, true, NR, RE>(a, s) : go_sv<C, true, false, false, NR, RE>(a, s);
   }
-  if (unit) return conj ? go_sv<C, false, true, true, NR>(a, s) : go_sv<C, false, true, false, NR>(a, s);
-  return conj ? go_sv<C, false, false, true, NR>(a, s) : go_sv<C, false, false, false, NR>(a, s);
+  if (unit) return conj ? go_sv<C, false, true, true, NR, RE>(a, s) : go_sv<C, false, true, false, NR, RE>(a, s);
+  return conj ? go_sv<C, false, false, true, NR, RE>(a, s) : go_sv<C, false, false, false, NR, RE>(a, s);
 }
 
 static inline int sv_nr(int64_t nrhs) { return nrhs >= 3 ? 4 : (int)nrhs; }
@@ -403,7 +437,7 @@ int64_t trsv_flag_words(int64_t n, int64_t nrhs) {
 }
 
 hipError_t launch_trsv(int C, bool lower, bool unit, bool conj, ZM Tm, ZM Xm, int64_t n,
-                       int64_t nrhs, int32_t *flags, hipStream_t s) {
+                       int64_t nrhs, int32_t *flags, hipStream_t s, bool real) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   const int NR = sv_nr(nrhs);
   SvArgs a;
@@ -416,11 +450,14 @@ hipError_t launch_trsv(int C, bool lower, bool unit, bool conj, ZM Tm, ZM Xm, in
   a.flags = flags;
   hipError_t e = launch_fill_i32(flags, 0, trsv_flag_words(n, nrhs), s);
   if (e != hipSuccess) return e;
-#define SV_NR(CC)                                                         \
-  switch (NR) {                                                           \
-    case 1: return dispatch_sv<CC, 1>(lower, unit, conj, a, s);           \
-    case 2: return dispatch_sv<CC, 2>(lower, unit, conj, a, s);           \
-    default: return dispatch_sv<CC, 4>(lower, unit, conj, a, s);          \
+#define SV_NR(CC)                                                                    \
+  switch (NR) {                                                                      \
+    case 1: return real ? dispatch_sv<CC, 1, true>(lower, unit, conj, a, s)          \
+                        : dispatch_sv<CC, 1, false>(lower, unit, conj, a, s);        \
+    case 2: return real ? dispatch_sv<CC, 2, true>(lower, unit, conj, a, s)          \
+                        : dispatch_sv<CC, 2, false>(lower, unit, conj, a, s);        \
+    default: return real ? dispatch_sv<CC, 4, true>(lower, unit, conj, a, s)         \
+                         : dispatch_sv<CC, 4, false>(lower, unit, conj, a, s);       \
   }
   switch (C) {
     case 2: SV_NR(2)
