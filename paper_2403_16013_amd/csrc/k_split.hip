@@ -240,7 +240,12 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
       __syncthreads();  // the buffer is refilled next
     }
     // level l (0-based) carries weight 2^(tau_i + tau_j - (l + 2) W); four consecutive
-    // levels span at most 24 + 3 W bits, so their scaled sum is exact in binary64
+    // levels span at most 24 + 3 W bits, so their scaled sum is exact in binary64.  A
+    // group starting at level lo is at most 2^(-lo W) of the largest possible level-0
+    // sum, so for TD and QD it enters the accumulator at component level lo W / 53: the
+    // TwoSum steps above that level would only pass it down unchanged.  (For DD the
+    // saving is one TwoSum per group, and the shorter code needed 326 instead of 216
+    // VGPRs, which halved the waves per SIMD.)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       int tsum = tsums[0][e];
@@ -249,13 +254,14 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
 #pragma unroll
       for (int top = S - 1; top >= 0; top -= 4) {
         const int lo = top - 3 < 0 ? 0 : top - 3;
+        const int lvl = C == 2 ? 0 : ((lo * W) / 53 < C - 1 ? (lo * W) / 53 : C - 1);
         double grp = 0.0;
 #pragma unroll
         for (int l = top; l >= lo; --l)
           grp = __builtin_fma((double)acc[l][e], ldexp(1.0, (lo - l) * W), grp);
         grp = ldexp(grp, tsum - (lo + 2) * W);
-        if (sr != 0.0) mp::push<C>(lr[e], 0, sr * grp);
-        mp::push<C>(li[e], 0, si * grp);
+        if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * grp);
+        mp::push<C>(li[e], lvl, si * grp);
       }
     }
   }
@@ -308,9 +314,12 @@ __global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
                          (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
 #pragma unroll
         for (int l = S - 1; l >= 0; --l) {
+          // level l is at most 2^(-l W) of the largest possible level-0 sum: it enters the
+          // accumulator at component level l W / 53 (as in k_split_i8)
+          const int lvl = (l * W) / 53 < C - 1 ? (l * W) / 53 : C - 1;
           const double v = ldexp(acc[l][e], tsum - (l + 2) * W);
-          if (sr != 0.0) mp::push<C>(lr[e], 0, sr * v);
-          mp::push<C>(li[e], 0, si * v);
+          if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * v);
+          mp::push<C>(li[e], lvl, si * v);
         }
       }
     }
