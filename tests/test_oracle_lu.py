@@ -85,19 +85,26 @@ def exact_solve(M, b):
 
 
 @pytest.mark.parametrize("C", CS)
-def test_tiny_lu_matches_exact_elimination(orc, C):
+@pytest.mark.parametrize("real", [False, True])
+def test_tiny_lu_matches_exact_elimination(orc, C, real):
     """Pin P2: n <= 6 random inputs.  The pivot sequence equals exact rational GEPP
     whenever every exact cabs1 gap exceeds 2^-90, PA - LU is within the rounding bound,
-    and the solution is within 10 n kappa u of the exact solution."""
+    and the solution is within 10 n kappa u of the exact solution.  With zero imaginary
+    parts (the oracle of the real routines) the factors stay real and the same holds
+    against real rational elimination."""
     u = U_FMT[C]
     checked = 0
     for seed in range(12):
         n = 2 + seed % 5
         A = orc.canon(synthgen.uniform(n, n, C, 100 + seed))
+        if real:
+            A[1] = 0.0
         M = to_frac_matrix(A)
         ipiv_x, F_x, gaps = exact_gepp(M)
         LU, ipiv, info = orc.getf2(A)
         assert info == 0
+        if real:
+            assert not np.any(LU[1])
         if min(gaps) > 2.0 ** -90:
             assert list(ipiv) == ipiv_x
             checked += 1
