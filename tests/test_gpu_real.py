@@ -103,7 +103,8 @@ def test_dgemm_exact_on_dyadic_data(mp):
 
 
 @pytest.mark.parametrize("C", CS)
-@pytest.mark.parametrize("shape", [(200, 200, 64), (150, 100, 32), (100, 150, 32)])
+@pytest.mark.parametrize("shape", [(200, 200, 64), (150, 100, 32), (100, 150, 32),
+                                   (260, 260, 128), (257, 200, 96)])
 def test_dgetrf_vs_oracle_and_schedules(mp, orc, C, shape):
     """The real factorisation against the oracle (pivots where the gap is clear, factors
     within 100 max(m, n) u), and the look-ahead schedule bitwise equal to the in-order one."""
