@@ -313,8 +313,8 @@ def panel_sweep(mp, torch, synthgen, n, panels, steps=2):
 
 def real_bench(mp, torch, synthgen, n, panel, steps=2):
     """Real DD / QD gesv (the Im = 0 case, mplu_dgesv) on the real part of the headline
-    matrix, b = A 1; effective GFLOPS from the real LU count 2 n^3 / 3; eta from the QD
-    residual of the complex embedding."""
+    matrix, b = A 1, with the real product and with the INT8 split; effective GFLOPS from
+    the real LU count 2 n^3 / 3; eta from the QD residual of the complex embedding."""
     out = {}
     for C in (2, 4):
         Z, _ = make_problem(mp, torch, synthgen, n, C)
@@ -322,28 +322,33 @@ def real_bench(mp, torch, synthgen, n, panel, steps=2):
         del Z
         X1 = torch.from_numpy(synthgen.ones(n, 1, C)[0]).cuda()
         B0 = mp.dgemm(A0, X1)
-        nb = ct.c_size_t()
-        o = mp._opts(panel, "3m")
-        mp.lib().mplu_dgesv_wsbytes(C, n, 1, ct.byref(o), ct.byref(nb))
-        work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
-        As = [A0.clone() for _ in range(steps + 1)]
-        Bs = [B0.clone() for _ in range(steps + 1)]
-        mp.dgesv(As[0], Bs[0], panel=panel, work=work)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        infos = [mp.dgesv(As[s], Bs[s], panel=panel, work=work)[1] for s in range(1, steps + 1)]
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
         emb = lambda R: torch.stack([R, torch.zeros_like(R)])
-        eta = backward_error(mp, torch, emb(A0), emb(Bs[-1]), emb(B0))
-        key = ["", "", "DD", "TD", "QD"][C]
-        out[key] = {"ms": round(ms, 3), "gflops": round(2.0 * n ** 3 / 3.0 / (ms / 1e3) / 1e9, 2),
-                    "eta": eta, "info": max(int(i.item()) for i in infos)}
-        print(f"[bench] real {key}: {out[key]}", file=sys.stderr, flush=True)
-        del As, Bs, A0, B0, work
+        for meth in ("3m", "split_i8"):
+            nb = ct.c_size_t()
+            o = mp._opts(panel, meth)
+            mp.lib().mplu_dgesv_wsbytes(C, n, 1, ct.byref(o), ct.byref(nb))
+            work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+            As = [A0.clone() for _ in range(steps + 1)]
+            Bs = [B0.clone() for _ in range(steps + 1)]
+            mp.dgesv(As[0], Bs[0], panel=panel, method=meth, work=work)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            infos = [mp.dgesv(As[s], Bs[s], panel=panel, method=meth, work=work)[1]
+                     for s in range(1, steps + 1)]
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            eta = backward_error(mp, torch, emb(A0), emb(Bs[-1]), emb(B0))
+            key = f"{['', '', 'DD', 'TD', 'QD'][C]}_{'real_product' if meth == '3m' else meth}"
+            out[key] = {"ms": round(ms, 3),
+                        "gflops": round(2.0 * n ** 3 / 3.0 / (ms / 1e3) / 1e9, 2),
+                        "eta": eta, "info": max(int(i.item()) for i in infos)}
+            print(f"[bench] real {key}: {out[key]}", file=sys.stderr, flush=True)
+            del As, Bs, work
+            torch.cuda.empty_cache()
+        del A0, B0
         torch.cuda.empty_cache()
     return {"n": n, "panel": panel, "op": "real gesv (mplu_dgesv), 1 RHS",
             "flops": "2 n^3 / 3 per factorisation", "results": out}

@@ -183,9 +183,10 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k,
  * the caller's C planes: the panel (pivot measure |a| in full precision, real
  * reciprocal), interchanges, triangular solves and substitutions, and the real product
  * (only T1 = Re(L21) Re(U12) of Eq. 3m_cemm) for the trailing and block updates.
- * opts->gemm must be MPLU_GEMM_4M or MPLU_GEMM_3M (both select the real product); the
- * split methods return MPLU_E_UNSUPPORTED.  Argument meaning, pivots, d_info, ownership,
- * errors and workspace sizes are as for the complex routines.
+ * opts->gemm: MPLU_GEMM_4M and MPLU_GEMM_3M both select the real product; the split
+ * methods split the real operands (one real product of digit pairs instead of three).
+ * Argument meaning, pivots, d_info, ownership, errors and workspace sizes are as for the
+ * complex routines.
  */
 typedef struct {
   double *planes;

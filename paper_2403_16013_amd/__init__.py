@@ -237,12 +237,13 @@ def _dmat(T: torch.Tensor) -> DMat:
     return DMat(T.data_ptr(), T.shape[2], T.shape[1] * T.shape[2])
 
 
-def dgetrf(A: torch.Tensor, panel: int = 64, m: int | None = None,
+def dgetrf(A: torch.Tensor, panel: int = 64, method="3m", m: int | None = None,
            work: torch.Tensor | None = None, lookahead: bool = True):
-    """In-place P A = L U of a real matrix.  Returns (ipiv, info) int32 device tensors."""
+    """In-place P A = L U of a real matrix ('3m' / '4m' select the real product, the split
+    methods split real operands).  Returns (ipiv, info) int32 device tensors."""
     C, n = A.shape[0], A.shape[1]
     m = A.shape[2] if m is None else m
-    o = _opts(panel, "3m", 0, 0, lookahead)
+    o = _opts(panel, method, 0, 0, lookahead)
     nb = ct.c_size_t()
     _check(lib().mplu_dgetrf_wsbytes(C, m, n, ct.byref(o), ct.byref(nb)), "wsbytes")
     if work is None or work.numel() < nb.value:
@@ -269,12 +270,12 @@ def dgetrs(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor, trans: str = "
     return B
 
 
-def dgesv(A: torch.Tensor, B: torch.Tensor, panel: int = 64, work: torch.Tensor | None = None,
-          lookahead: bool = True):
+def dgesv(A: torch.Tensor, B: torch.Tensor, panel: int = 64, method="3m",
+          work: torch.Tensor | None = None, lookahead: bool = True):
     """Real A X = B in place: A := factors, B := X.  Returns (ipiv, info)."""
     C, n = A.shape[0], A.shape[1]
     nrhs = B.shape[1]
-    o = _opts(panel, "3m", 0, 0, lookahead)
+    o = _opts(panel, method, 0, 0, lookahead)
     nb = ct.c_size_t()
     _check(lib().mplu_dgesv_wsbytes(C, n, nrhs, ct.byref(o), ct.byref(nb)), "wsbytes")
     if work is None or work.numel() < nb.value:

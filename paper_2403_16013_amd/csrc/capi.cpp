@@ -142,21 +142,25 @@ hipError_t step_trsm(int C, ZM a, int64_t j, int jb, int64_t c0, int64_t c1, hip
   return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s, swl, 2 * jb, real);
 }
 
+// real: a real matrix (the split methods then split real operands; the others use the
+// real product)
 hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
-                     int64_t c1, void *split_ws, hipStream_t s) {
+                     int64_t c1, void *split_ws, hipStream_t s, bool real) {
   if (c1 <= c0 || j + jb >= m) return hipSuccess;
   if (is_split(method))
     return launch_gemm_split(C, method == MPLU_GEMM_SPLIT_I8, S, 'N', 'N', m - j - jb, c1 - c0,
-                             jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, split_ws, s);
+                             jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, split_ws, s,
+                             real);
+  if (real) method = kGemmReal;
   return launch_gemm(C, method == kGemmReal ? 2 : (method == MPLU_GEMM_3M ? 1 : 0), 'N', 'N',
                      m - j - jb, c1 - c0, jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, s);
 }
 
 hipError_t step_update(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
-                       int64_t c1, void *split_ws, hipStream_t s) {
-  hipError_t e = step_trsm(C, a, j, jb, c0, c1, s, nullptr, method == kGemmReal);
+                       int64_t c1, void *split_ws, hipStream_t s, bool real) {
+  hipError_t e = step_trsm(C, a, j, jb, c0, c1, s, nullptr, real);
   if (e != hipSuccess) return e;
-  return step_gemm(C, method, S, a, m, j, jb, c0, c1, split_ws, s);
+  return step_gemm(C, method, S, a, m, j, jb, c0, c1, split_ws, s, real);
 }
 
 // ------------------------------------------------------------------ Strassen-Winograd
@@ -307,7 +311,6 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M && method != MPLU_GEMM_SPLIT_F64 &&
       method != MPLU_GEMM_SPLIT_I8)
     return -7;
-  if (real && method != MPLU_GEMM_4M && method != MPLU_GEMM_3M) return MPLU_E_UNSUPPORTED;
   if (!split_opts_ok(prec, method, opts)) return MPLU_E_UNSUPPORTED;
   size_t need = 0;
   getrf_ws(prec, m, n, opts, &need);
@@ -331,7 +334,6 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   void *split_rest = wb + 3 * L.panel;
   void *split_next = wb + 3 * L.panel + L.split_rest;
   const int S = opts ? opts->n_slices : 0;
-  const int upd = real ? kGemmReal : method;
 
   unsigned base[3] = {0u, 0u, 0u};
   for (int i = 0; i < 3; ++i) HIPCHK(panel_ws_clear(pws[i], s));
@@ -340,7 +342,7 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
       const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
       HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, pws[0], &base[0], s, real));
       HIPCHK(launch_laswp(C, a, j, j + jb, n, pws[0], jb, s, real));
-      HIPCHK(step_update(C, upd, S, a, m, j, jb, j + jb, n, split_rest, s));
+      HIPCHK(step_update(C, method, S, a, m, j, jb, j + jb, n, split_rest, s, real));
     }
     return 0;
   }
@@ -371,14 +373,14 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     if (nx1 > nx0) {
       // the next panel's columns: interchanges and U12 in one launch, then the product
       HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb), real));
-      HIPCHK(step_gemm(C, upd, S, a, m, j, jb, nx0, nx1, split_next, s));
+      HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx0, nx1, split_next, s, real));
     }
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device
     HIPCHK(hipEventRecord(sd->ev_chain, s));
     HIPCHK(step_trsm(C, a, j, jb, nx1, n, b, panel_swap_list(pw, C, jb), real));
     HIPCHK(hipStreamWaitEvent(b, sd->ev_chain, 0));
-    HIPCHK(step_gemm(C, upd, S, a, m, j, jb, nx1, n, split_rest, b));
+    HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx1, n, split_rest, b, real));
     HIPCHK(hipEventRecord(sd->ev_rest, b));
     // panel k's interchanges on the columns left of it; the workspace holding the list is
     // next written by panel k+3, which the caller's stream starts only after the second

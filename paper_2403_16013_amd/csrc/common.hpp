@@ -152,10 +152,11 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
 int split_slices(int C, bool i8);
 bool split_supported(int C, bool i8, int S);
 size_t split_ws_bytes(int C, bool i8, int64_t m, int64_t n, int64_t K, int S);
+// (real: real operands and result, C planes; one real product instead of three)
 hipError_t launch_gemm_split(int C, bool i8, int S, char opA, char opB, int64_t m, int64_t n,
                              int64_t k, int alpha, ZM A, int64_t ai, int64_t aj, ZM B,
                              int64_t bi, int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj,
-                             void *ws, hipStream_t s);
+                             void *ws, hipStream_t s, bool real = false);
 
 // op(T) X = X for the whole n x n triangle of Tm and nrhs columns of Xm in one launch;
 // flags: trsv_flag_words(n, nrhs) int32 of workspace (cleared by the launcher)

@@ -36,9 +36,17 @@ struct SliceArgs {
   int32_t *tau;   // [3][nvec]
 };
 
-template <int C>
+// RE: a real operand; only x[0] (its value) is formed
+template <int C, bool RE>
 __device__ __forceinline__ void slice_elem(const SliceArgs &a, int64_t v, int64_t t,
                                            double (&x)[3][C]) {
+  if (RE) {
+    double re[C];
+    if (a.trans) ld_re<C>(a.M, a.i0 + t, a.j0 + v, re);
+    else ld_re<C>(a.M, a.i0 + v, a.j0 + t, re);
+    mp::renorm<C>(re, x[0]);
+    return;
+  }
   double re[C], im[C];
   if (a.trans) ld_z<C>(a.M, a.i0 + t, a.j0 + v, re, im);
   else ld_z<C>(a.M, a.i0 + v, a.j0 + t, re, im);
@@ -57,22 +65,24 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// one wave per vector
-template <int C, int W, int S, typename T>
+// one wave per vector; NO operand sets: the three of Eq. 3m_cemm (Re, Im, Re + Im), or
+// one for a real operand
+template <int C, int W, int S, typename T, int NO>
 __global__ __launch_bounds__(256) void k_slice(SliceArgs a) {
+  constexpr bool RE = NO == 1;
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (v >= a.nvec) return;
   double mx[3] = {0.0, 0.0, 0.0};
   for (int64_t t = lane; t < a.K; t += 64) {
     double x[3][C];
-    slice_elem<C>(a, v, t, x);
+    slice_elem<C, RE>(a, v, t, x);
 #pragma unroll
-    for (int o = 0; o < 3; ++o) mx[o] = fmax(mx[o], fabs(x[o][0]));
+    for (int o = 0; o < NO; ++o) mx[o] = fmax(mx[o], fabs(x[o][0]));
   }
   int tau[3];
 #pragma unroll
-  for (int o = 0; o < 3; ++o) {
+  for (int o = 0; o < NO; ++o) {
     const double m = wave_max(mx[o]);
     int e = 0;
     if (m > 0.0) frexp(m, &e);  // m < 2^e, hence every entry (with its tail) < 2^e
@@ -83,15 +93,15 @@ __global__ __launch_bounds__(256) void k_slice(SliceArgs a) {
   for (int64_t t = lane; t < a.Kpad; t += 64) {
     double x[3][C];
     if (t < a.K) {
-      slice_elem<C>(a, v, t, x);
+      slice_elem<C, RE>(a, v, t, x);
     } else {
 #pragma unroll
-      for (int o = 0; o < 3; ++o)
+      for (int o = 0; o < NO; ++o)
 #pragma unroll
         for (int c = 0; c < C; ++c) x[o][c] = 0.0;
     }
 #pragma unroll
-    for (int o = 0; o < 3; ++o) {
+    for (int o = 0; o < NO; ++o) {
       double r[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) r[c] = x[o][c];
@@ -130,13 +140,24 @@ __device__ __forceinline__ void op_signs(int op, double &sr, double &si) {
   si = (op == 2) ? 1.0 : -1.0;
 }
 
-template <int C>
+template <int C, bool RE>
 __device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t nj,
                                          double (&lr)[C], double (&li)[C]) {
   if (mi >= g.m || nj >= g.n) return;
   if (g.alpha < 0) {
 #pragma unroll
     for (int c = 0; c < C; ++c) { lr[c] = -lr[c]; li[c] = -li[c]; }
+  }
+  if (RE) {  // real: only the real planes
+    if (g.beta) {
+      double cr[C];
+      ld_re<C>(g.Cm, g.ci + mi, g.cj + nj, cr);
+      mp::push_mp<C>(lr, cr);
+    }
+    double orr[C];
+    mp::renorm<C>(lr, orr);
+    st_re<C>(g.Cm, g.ci + mi, g.cj + nj, orr);
+    return;
   }
   if (g.beta) {
     double cr[C], cim[C];
@@ -163,9 +184,10 @@ __device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t
 // or flushes its levels; this measured faster than a second buffer per workgroup.  Rows
 // and columns past the edge load the last valid one: they only reach outputs that are
 // never stored.
-template <int C, int S>
+template <int C, int S, int NO>
 __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   constexpr int W = 7;
+  constexpr bool RE = NO == 1;
   constexpr int PL = S * 32 * 4;            // 16-byte pieces per operand per chunk
   extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -187,7 +209,7 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   // front so the per-product flush does not wait on memory
   int tsums[3][4];
 #pragma unroll
-  for (int op = 0; op < 3; ++op)
+  for (int op = 0; op < NO; ++op)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
@@ -215,9 +237,10 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
           (__attribute__((address_space(3))) void *)(dY + e0), 16, 0, 0);
     }
   };
-  for (int op = 0; op < 3; ++op) {
+  for (int op = 0; op < NO; ++op) {
     double sr, si;
     op_signs(op, sr, si);
+    if (RE) si = 0.0;  // a real product has no imaginary part
     v4i acc[S];
 #pragma unroll
     for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
@@ -250,7 +273,7 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
     for (int e = 0; e < 4; ++e) {
       int tsum = tsums[0][e];
 #pragma unroll
-      for (int o = 1; o < 3; ++o) tsum = (op == o) ? tsums[o][e] : tsum;
+      for (int o = 1; o < NO; ++o) tsum = (op == o) ? tsums[o][e] : tsum;
 #pragma unroll
       for (int top = S - 1; top >= 0; top -= 4) {
         const int lo = top - 3 < 0 ? 0 : top - 3;
@@ -261,19 +284,20 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
           grp = __builtin_fma((double)acc[l][e], ldexp(1.0, (lo - l) * W), grp);
         grp = ldexp(grp, tsum - (lo + 2) * W);
         if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * grp);
-        mp::push<C>(li[e], lvl, si * grp);
+        if (!RE) mp::push<C>(li[e], lvl, si * grp);
       }
     }
   }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) epilogue<C>(g, m0 + 4 * (lane >> 4) + e, bcol, lr[e], li[e]);
+  for (int e = 0; e < 4; ++e) epilogue<C, RE>(g, m0 + 4 * (lane >> 4) + e, bcol, lr[e], li[e]);
 }
 
 // FP64 digits, W = 22, K processed in blocks of 128 (the exactness limit of one level).
 // D layout of the 16x16x4 FP64 MFMA: element (4 e + lane/16, lane % 16) in register e.
-template <int C, int S>
+template <int C, int S, int NO>
 __global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
   constexpr int W = 22;
+  constexpr bool RE = NO == 1;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t m0 = (int64_t)blockIdx.y * 32 + 16 * (w >> 1);
   const int64_t n0 = (int64_t)blockIdx.x * 32 + 16 * (w & 1);
@@ -286,9 +310,10 @@ __global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
 #pragma unroll
     for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
 
-  for (int op = 0; op < 3; ++op) {
+  for (int op = 0; op < NO; ++op) {
     double sr, si;
     op_signs(op, sr, si);
+    if (RE) si = 0.0;
     for (int64_t kb = 0; kb < g.Kpad; kb += 128) {
       const int64_t kend = (kb + 128 < g.Kpad) ? kb + 128 : g.Kpad;
       v4d acc[S];
@@ -319,13 +344,13 @@ __global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
           const int lvl = (l * W) / 53 < C - 1 ? (l * W) / 53 : C - 1;
           const double v = ldexp(acc[l][e], tsum - (l + 2) * W);
           if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * v);
-          mp::push<C>(li[e], lvl, si * v);
+          if (!RE) mp::push<C>(li[e], lvl, si * v);
         }
       }
     }
   }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) epilogue<C>(g, m0 + 4 * e + (lane >> 4), bcol, lr[e], li[e]);
+  for (int e = 0; e < 4; ++e) epilogue<C, RE>(g, m0 + 4 * e + (lane >> 4), bcol, lr[e], li[e]);
 }
 
 // ------------------------------------------------------------------ host side
@@ -351,7 +376,9 @@ size_t split_ws_bytes(int C, bool i8, int64_t m, int64_t n, int64_t K, int S) {
   return b;
 }
 
-template <int C, int S, bool I8>
+// NO = 3 operand sets (complex, Eq. 3m_cemm) or 1 (real); the workspace layout is the
+// complex one in both cases
+template <int C, int S, bool I8, int NO>
 static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int alpha, ZM A,
                       int64_t ai, int64_t aj, ZM B, int64_t bi, int64_t bj, int beta, ZM Cm,
                       int64_t ci, int64_t cj, void *ws, hipStream_t s) {
@@ -371,8 +398,8 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
   sx.tau = (int32_t *)p;
   p += al256(sizeof(int32_t) * 3 * (size_t)m);
   sy.tau = (int32_t *)p;
-  hipLaunchKernelGGL((k_slice<C, W, S, T>), dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, sx);
-  hipLaunchKernelGGL((k_slice<C, W, S, T>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, sy);
+  hipLaunchKernelGGL((k_slice<C, W, S, T, NO>), dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, sx);
+  hipLaunchKernelGGL((k_slice<C, W, S, T, NO>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, sy);
   SplitArgs g;
   g.xs = sx.out; g.ys = sy.out; g.tx = sx.tau; g.ty = sy.tau;
   g.m = m; g.n = n; g.Kpad = Kp;
@@ -382,11 +409,11 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
     const dim3 grid1((unsigned)(((n + 31) / 32) * ((m + 31) / 32)));
     const size_t lds = sizeof(v4i) * 2 * S * 32 * 4;
     static LdsAttr attr;
-    const hipError_t e = attr.ensure((const void *)k_split_i8<C, S>, (int)lds);
+    const hipError_t e = attr.ensure((const void *)k_split_i8<C, S, NO>, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_split_i8<C, S>), grid1, dim3(256), lds, s, g);
+    hipLaunchKernelGGL((k_split_i8<C, S, NO>), grid1, dim3(256), lds, s, g);
   } else {
-    hipLaunchKernelGGL((k_split_f64<C, S>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_split_f64<C, S, NO>), grid, dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }
@@ -394,10 +421,12 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
 hipError_t launch_gemm_split(int C, bool i8, int S, char opA, char opB, int64_t m, int64_t n,
                              int64_t k, int alpha, ZM A, int64_t ai, int64_t aj, ZM B,
                              int64_t bi, int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj,
-                             void *ws, hipStream_t s) {
+                             void *ws, hipStream_t s, bool real) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (S <= 0) S = split_slices(C, i8);
-#define RUN(CC, SS, II) return run<CC, SS, II>(opA, opB, m, n, k, alpha, A, ai, aj, B, bi, bj, beta, Cm, ci, cj, ws, s)
+#define RUN(CC, SS, II)                                                                      \
+  return real ? run<CC, SS, II, 1>(opA, opB, m, n, k, alpha, A, ai, aj, B, bi, bj, beta, Cm, ci, cj, ws, s) \
+              : run<CC, SS, II, 3>(opA, opB, m, n, k, alpha, A, ai, aj, B, bi, bj, beta, Cm, ci, cj, ws, s)
   if (i8) {
     if (C == 2 && S == 17) RUN(2, 17, true);
     if (C == 3 && S == 24) RUN(3, 24, true);

@@ -85,9 +85,10 @@ def test_argument_checks(L):
     bad = m.Opts(-1, 1, 0, 0, 0)
     assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
     assert L.mplu_dgesv(2, 8, 1, d, ip, d, inf, ct.byref(bad), wk, 1 << 30, None) == -8
-    split = m.Opts(64, 3, 0, 0, 0)   # the split methods have no real form
+    split = m.Opts(64, 3, 99, 0, 0)   # a slice count the split kernels do not have
     assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, ct.byref(split), wk, 1 << 30, None) == -102
     assert L.mplu_dgesv(2, 8, 1, d, ip, d, inf, ct.byref(split), wk, 1 << 30, None) == -102
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(split), wk, 1 << 30, None) == -102
     assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, None, ct.c_void_p(0x10001), 1 << 30, None) == -8
     assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, None, wk, 16, None) == -100
     assert L.mplu_dgetrs(2, b"C", 8, 1, d, ip, d, wk, 1 << 30, None) == -2

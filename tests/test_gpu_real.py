@@ -241,3 +241,41 @@ def test_real_empty_and_tiny(mp, orc):
         Xo = orc.getrs(*orc.getf2(embed(A))[:2], embed(B))
         d = orc.diff(embed(host(Bd)), Xo)
         assert np.abs(d).max() <= 8 * U_FMT[C] * np.abs(orc.hi_complex(Xo)).max()
+
+
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("method", ["split_i8", "split_f64"])
+def test_real_split_lu_vs_oracle(mp, orc, C, method):
+    """The split trailing update on real operands: solution and backward error against
+    the oracle, the look-ahead schedule bitwise equal to the in-order one, and exact
+    dyadic factorisations bit for bit."""
+    n = 200
+    A = real_planes(n, n, C, 140 + C, orc)
+    B = real_planes(n, 2, C, 150 + C, orc)
+    LUo, ipo, _ = orc.getf2(embed(A))
+    Xo = orc.getrs(LUo, ipo, embed(B))
+    Ad, Bd = dev(A), dev(B)
+    ipiv, info = mp.dgesv(Ad, Bd, panel=64, method=method)
+    A2 = dev(A)
+    ipiv2, _ = mp.dgetrf(A2, panel=64, method=method, lookahead=False)
+    sync()
+    assert int(info.item()) == 0
+    assert np.array_equal(host(Ad), host(A2))
+    assert np.array_equal(ipiv.cpu().numpy(), ipiv2.cpu().numpy())
+    Xg = embed(host(Bd))
+    kappa = float(np.linalg.cond(A[0].T, np.inf))
+    d = orc.diff(Xg, Xo)
+    assert np.abs(d).max() / np.abs(orc.hi_complex(Xo)).max() <= 10 * n * kappa * U_FMT[C]
+    assert orc.backward_error(embed(A), Xg, embed(B)) <= 10 * n * U_FMT[C]
+    # exactly representable: L dyadic with |l| <= 1/4, U dyadic, power-of-two diagonal
+    rng = np.random.default_rng(160 + C)
+    m = 150
+    L = np.eye(m) + np.tril(rng.integers(-64, 65, (m, m)) / 256.0, -1)
+    U = np.triu(rng.integers(-256, 257, (m, m)) / 256.0, 1)
+    U[np.diag_indices(m)] = 2.0 ** rng.integers(-2, 3, m) * rng.choice([-1, 1], m)
+    P = lambda X: synthgen.planes_from_complex(np.asarray(X, dtype=complex), C)[0]
+    Ed = dev(P(L @ U))
+    _, info = mp.dgetrf(Ed, panel=32, method=method)
+    sync()
+    assert int(info.item()) == 0
+    assert np.array_equal(host(Ed)[0].T, np.tril(L, -1) + U)
