@@ -63,7 +63,10 @@ typedef struct {
 
 /* Options; a NULL pointer selects the defaults given in brackets. */
 typedef struct {
-  int32_t panel;      /* panel width K (= NDIM of Sec. 3) [64]; >= n gives the unblocked LU */
+  int32_t panel;      /* panel width K (= NDIM of Sec. 3) [64], at most 128 (the panel is
+                         held in LDS); >= min(m, n) gives the unblocked LU, which therefore
+                         needs min(m, n) <= 128; an effective width min(panel, min(m, n))
+                         above 128 makes mplu_zgetrf return MPLU_E_UNSUPPORTED          */
   int32_t gemm;       /* mplu_gemm_t for the trailing update [MPLU_GEMM_3M]                 */
   int32_t n_slices;   /* split methods: slices per operand, 0 = automatic                   */
   int32_t slice_bits; /* split methods: bits per slice, 0 = automatic                       */

@@ -324,3 +324,83 @@ def gen_illcond(n: int, C: int, sigma: np.ndarray, VL: np.ndarray, VR: np.ndarra
     if rc != 0:
         raise RuntimeError(f"orc_gen_illcond failed: {rc}")
     return A
+
+
+def solve_grad(LU: np.ndarray, ipiv: np.ndarray, X: np.ndarray, Gx: np.ndarray,
+               threads: int = 0):
+    """Gradient of a real loss through x = A^-1 b, from the oracle's own factors.
+
+    With the complex convention g = dL/dRe + i dL/dIm, differentiating A x = b gives
+        g_b = A^-H g_x                 (a conjugate-transpose solve with getf2's factors)
+        g_A = -g_b x^H                 (each element the exact product, rounded once)
+    LU, ipiv: getf2's output for A; X: the solution (n x nrhs); Gx: dL/dx (n x nrhs).
+    Returns (g_b, g_A) as plane arrays of the format of LU."""
+    C, n, ld, _ = _geom(LU)
+    _, nrhs, _, _ = _geom(Gx)
+    Gb = getrs(LU, ipiv, Gx, "C", threads=threads)
+    GA = gemm(Gb, X, None, method=4, opA="N", opB="C", alpha_sign=-1, m=n, n=n, k=nrhs,
+              threads=threads)
+    return Gb, GA
+
+
+def _planes_of(z: np.ndarray, C: int) -> np.ndarray:
+    """complex128 vector -> (2, C, 1, n) planes with zero lower components."""
+    P = np.zeros((2, C, 1, z.shape[0]))
+    P[0, 0, 0] = z.real
+    P[1, 0, 0] = z.imag
+    return P
+
+
+def inv_norm1_est(LU: np.ndarray, ipiv: np.ndarray, trans: str = "N", itmax: int = 5,
+                  threads: int = 0) -> float:
+    """Estimate ||B||_1 for B = A^-1 (trans 'N') or B = A^-H (trans 'C') from getf2's
+    factors, by the 1-norm power method of Hager (1984) with Higham's (1988) refinements
+    for complex matrices: it only needs products with B and B^H, i.e. solves with A.
+
+      x = e / n;  repeat:  y = B x,  xi_i = y_i / |y_i| (1 where y_i = 0),  z = B^H xi;
+                           stop when ||z||_inf <= Re(z^H x) or the index repeats;
+                           otherwise x = e_j with j the first index maximising |z_j|;
+      then compare with 2 ||B w||_1 / (3 n) for w_i = (-1)^i (1 + i / (n - 1)), which
+      guards against the cases where the power method stalls.
+
+    The solves run in the oracle's multi-component arithmetic; the norms of the leading
+    components suffice for an estimate.  The value is a lower bound of ||B||_1 (up to
+    rounding), usually equal to it."""
+    C, n, _, _ = _geom(LU)
+    if n == 0:
+        return 0.0
+    other = "C" if trans == "N" else "N"
+
+    def apply(z, tr):
+        out = getrs(LU, ipiv, _planes_of(z, C), tr, threads=threads)
+        return out[0, 0, 0] + 1j * out[1, 0, 0]
+
+    x = np.full(n, 1.0 / n, dtype=complex)
+    est, jlast = 0.0, -1
+    for it in range(itmax):
+        y = apply(x, trans)
+        new = float(np.abs(y).sum())
+        if it > 0 and new <= est:
+            break
+        est = new
+        a = np.abs(y)
+        xi = np.where(a > 0, y / np.where(a > 0, a, 1.0), 1.0)
+        z = apply(xi, other)
+        j = int(np.argmax(np.abs(z)))
+        if np.abs(z).max() <= float(np.real(np.vdot(z, x))) or j == jlast:
+            break
+        x = np.zeros(n, dtype=complex)
+        x[j] = 1.0
+        jlast = j
+    i = np.arange(n, dtype=float)
+    w = ((-1.0) ** i) * (1.0 + i / max(1, n - 1))
+    alt = 2.0 * float(np.abs(apply(w.astype(complex), trans)).sum()) / (3.0 * n)
+    return max(est, alt)
+
+
+def cond_inf_est(A: np.ndarray, LU: np.ndarray, ipiv: np.ndarray, threads: int = 0) -> float:
+    """kappa_inf(A) = ||A||_inf ||A^-1||_inf, the second factor estimated as ||A^-H||_1
+    (inv_norm1_est on A^H) from getf2's factors of A; ||A||_inf from the leading
+    components (complex modulus)."""
+    nA = float(np.abs(hi_complex(A)).sum(axis=1).max())
+    return nA * inv_norm1_est(LU, ipiv, "C", threads=threads)

@@ -312,6 +312,12 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
       method != MPLU_GEMM_SPLIT_I8)
     return -7;
   if (!split_opts_ok(prec, method, opts)) return MPLU_E_UNSUPPORTED;
+  {
+    // the panel is held in LDS: widths up to kMaxPanel (a width >= min(m, n) asks for the
+    // unblocked factorisation, so it needs min(m, n) <= kMaxPanel)
+    const int64_t req = (opts && opts->panel > 0) ? opts->panel : kDefaultPanel;
+    if ((req < mn ? req : mn) > kMaxPanel) return MPLU_E_UNSUPPORTED;
+  }
   size_t need = 0;
   getrf_ws(prec, m, n, opts, &need);
   if (d_work == nullptr || ((uintptr_t)d_work & 255u)) return -8;

@@ -366,8 +366,15 @@ static inline int64_t kpad_of(int64_t K, bool i8) {
   return ((K + q - 1) / q) * q;
 }
 
+// Depth of one INT8 split product.  A level sum of k_split_i8 gains at most 64 S 65^2 per
+// 64-deep chunk (S digit pairs of at most 65 x 65 at the top level), so it stays below
+// 2^31 for floor((2^31 - 1) / (64 S 65^2)) chunks: 467 (DD), 330 (TD), 248 (QD), i.e.
+// k up to 29 888, 21 120, 15 872.
+static int64_t split_i8_max_k(int S) { return (2147483647ll / (64ll * S * 65 * 65)) * 64; }
+
 size_t split_ws_bytes(int C, bool i8, int64_t m, int64_t n, int64_t K, int S) {
   if (S <= 0) S = split_slices(C, i8);
+  if (i8 && K > split_i8_max_k(S)) K = split_i8_max_k(S);  // deeper products run in pieces
   const size_t el = i8 ? 1 : 8;
   const int64_t Kp = kpad_of(K, i8);
   size_t b = al256(el * 3 * (size_t)S * (size_t)m * (size_t)Kp);
@@ -424,6 +431,20 @@ hipError_t launch_gemm_split(int C, bool i8, int S, char opA, char opB, int64_t 
                              void *ws, hipStream_t s, bool real) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (S <= 0) S = split_slices(C, i8);
+  if (i8 && k > split_i8_max_k(S)) {
+    // deeper products run as consecutive pieces accumulated into Cm (beta = 1 after the
+    // first); each piece adds one rounding of the running sum
+    const int64_t kp = split_i8_max_k(S);
+    for (int64_t k0 = 0; k0 < k; k0 += kp) {
+      const int64_t kk = k - k0 < kp ? k - k0 : kp;
+      const bool ta = opA != 'N', tb = opB != 'N';
+      const hipError_t e = launch_gemm_split(
+          C, i8, S, opA, opB, m, n, kk, alpha, A, ai + (ta ? k0 : 0), aj + (ta ? 0 : k0), B,
+          bi + (tb ? 0 : k0), bj + (tb ? k0 : 0), k0 == 0 ? beta : 1, Cm, ci, cj, ws, s, real);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
 #define RUN(CC, SS, II)                                                                      \
   return real ? run<CC, SS, II, 1>(opA, opB, m, n, k, alpha, A, ai, aj, B, bi, bj, beta, Cm, ci, cj, ws, s) \
               : run<CC, SS, II, 3>(opA, opB, m, n, k, alpha, A, ai, aj, B, bi, bj, beta, Cm, ci, cj, ws, s)

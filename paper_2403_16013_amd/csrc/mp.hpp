@@ -294,10 +294,32 @@ __host__ __device__ __forceinline__ void zmul(const double (&ar)[C], const doubl
   renorm<C>(xi, oi);
 }
 
-// 1/b = conj(b) / (Re b^2 + Im b^2)
+// 2^-e for the exponent e of the larger leading component of b (clamped so that the scale
+// stays a normal number); 1 for zero, infinite or NaN leading components
+__host__ __device__ __forceinline__ double recip_scale(double r0, double i0) {
+  const double m = fabs(r0) > fabs(i0) ? fabs(r0) : fabs(i0);
+  const long long bits = __builtin_bit_cast(long long, m);
+  int e = (int)((bits >> 52) & 0x7ff);
+  e = (e == 0 || e == 0x7ff) ? 0 : e - 1023;
+  e = e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+  return __builtin_bit_cast(double, (long long)(1023 - e) << 52);
+}
+
+// 1/b = conj(b) / (Re b^2 + Im b^2), with b first scaled by an exact power of two s near
+// 1/|b| so that the squares neither overflow nor push lower components below the
+// normal range: 1/b = s * (1/(s b)).  Every step is exact under scaling by a power of two
+// while nothing over- or underflows, so for moderate |b| the result is bit for bit that of
+// the unscaled formula.
 template <int C>
-__host__ __device__ __forceinline__ void zrecip(const double (&br)[C], const double (&bi)[C],
+__host__ __device__ __forceinline__ void zrecip(const double (&br_)[C], const double (&bi_)[C],
                                        double (&or_)[C], double (&oi)[C]) {
+  const double s = recip_scale(br_[0], bi_[0]);
+  double br[C], bi[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    br[k] = br_[k] * s;
+    bi[k] = bi_[k] * s;
+  }
   double l[C];
   set_zero<C>(l);
   mac<C>(l, br, br);
@@ -309,6 +331,11 @@ __host__ __device__ __forceinline__ void zrecip(const double (&br)[C], const dou
   neg<C>(bi, nbi);
   mul<C>(br, inv, or_);
   mul<C>(nbi, inv, oi);
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    or_[k] *= s;
+    oi[k] *= s;
+  }
 }
 
 // cabs1 = |Re| + |Im| in full precision

@@ -105,6 +105,12 @@ def test_argument_checks(L):
     assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 0, z, 5, None, wk, 0, None) == -12
     st = m.Opts(64, 4, 0, 0, 0)
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(st), wk, 1 << 30, None) == -7
+    # panel widths above 128 (the LDS-resident panel) are refused, not clamped; a width
+    # >= min(m, n) asks for the unblocked LU, possible only for min(m, n) <= 128
+    big = m.ZMat(0x1000, 4096, 4096 * 4096)
+    for pw, nn in ((256, 512), (129, 4096), (4096, 4096), (200, 200)):
+        wide = m.Opts(pw, 1, 0, 0, 0)
+        assert L.mplu_zgetrf(2, nn, nn, big, ip, inf, ct.byref(wide), wk, 1 << 40, None) == -102
     assert L.mplu_zrenorm(2, 8, 8, null, None) == -4
     assert L.mplu_zconvert(2, 7, 8, 8, z, z, None) == -2
 
@@ -126,6 +132,15 @@ def test_workspace_queries(L):
     g = ct.c_size_t()
     assert L.mplu_zgemm_wsbytes(2, 4096, 4096, 128, 3, ct.byref(o3), ct.byref(g)) == 0
     assert i8 >= g.value
+    # INT8 split products deeper than the INT32 limit of a level sum (15 872 for QD) run in
+    # pieces of that depth, so their workspace stops growing there
+    deep, piece = ct.c_size_t(), ct.c_size_t()
+    assert L.mplu_zgemm_wsbytes(4, 64, 64, 40000, 3, None, ct.byref(deep)) == 0
+    assert L.mplu_zgemm_wsbytes(4, 64, 64, 15872, 3, None, ct.byref(piece)) == 0
+    assert deep.value == piece.value
+    assert L.mplu_zgemm_wsbytes(4, 64, 64, 15936, 3, None, ct.byref(deep)) == 0
+    assert L.mplu_zgemm_wsbytes(4, 64, 64, 15808, 3, None, ct.byref(g)) == 0
+    assert g.value < piece.value
     assert L.mplu_zgetrs_wsbytes(2, 100, 3, ct.byref(sz)) == 0
     assert sz.value >= 100 * 3 * 4 * 8
     assert L.mplu_zgesv_wsbytes(3, 100, 3, None, ct.byref(sz)) == 0

@@ -184,3 +184,35 @@ def test_long_same_sign_dot_with_tidy(H, C):
     o = arr([0] * C)
     H.mph_dot_tidy(C, n, 16, arr(sum(a, [])), arr(sum(b, [])), o)
     assert abs(fr(list(o)) - ex) <= 4 * (n + 2) * u * ex
+
+
+@pytest.mark.parametrize("C", CS)
+def test_complex_reciprocal_extreme_magnitudes(H, C):
+    """1/b for pivots of magnitude 2^+-230 .. 2^+-800 (about 1e+-70 .. 1e+-240), where
+    the unscaled Re b^2 + Im b^2 overflows, underflows or has subnormal lower
+    components: the result is finite and equals, bit for bit, 2^-k times the reciprocal
+    of the same value at moderate magnitude, so it is exactly as accurate as there."""
+    rng = np.random.default_rng(90 + C)
+    o1, o2 = arr([0] * (2 * C)), arr([0] * (2 * C))
+    for k in (-800, -600, -400, -230, 230, 400, 600, 800):
+        for t in range(40):
+            b = rand_mp(rng, C) + rand_mp(rng, C)
+            H.mph_zrecip(C, arr(b), o1)
+            H.mph_zrecip(C, arr([float(np.ldexp(x, k)) for x in b]), o2)
+            got = list(o2)
+            assert all(np.isfinite(got)), (k, t, got)
+            assert [float(np.ldexp(x, -k)) for x in list(o1)] == got, (k, t)
+
+
+@pytest.mark.parametrize("C", CS)
+def test_complex_reciprocal_scaling_is_exact(H, C):
+    """At moderate magnitudes the power-of-two scaling changes no bit: 1/(2^k b) equals
+    2^-k (1/b) exactly, componentwise."""
+    rng = np.random.default_rng(95 + C)
+    o1, o2 = arr([0] * (2 * C)), arr([0] * (2 * C))
+    for t in range(200):
+        b = rand_mp(rng, C) + rand_mp(rng, C)
+        k = int(rng.integers(-40, 40))
+        H.mph_zrecip(C, arr(b), o1)
+        H.mph_zrecip(C, arr([float(np.ldexp(x, k)) for x in b]), o2)
+        assert [float(np.ldexp(x, -k)) for x in list(o1)] == list(o2)
