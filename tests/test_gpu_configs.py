@@ -2,8 +2,9 @@
 size (the oracle's own LU would take minutes to hours here):
 
   C1  DD n=64, unblocked (panel = n), 4M, x = 1: elementwise against the oracle
-  C2  DD n=1024, panel 64, 3M and 4M, x = 1: eta, forward error, 3M-vs-4M agreement and
-      the imaginary-part residual growth of 3M
+  C2  DD n=1024, panel 64, 3M and 4M, x = 1: eta, forward error against x = 1 and
+      against the oracle's solution (kappa from the oracle's condition estimate),
+      3M-vs-4M agreement and the imaginary-part residual growth of 3M
   C3  TD and QD n=2048, panel 64, A = U diag(sigma) V^H with sigma from 1 to 1e-30, four
       right-hand sides (ones, k + k i, two random DD columns): eta and forward error
       against kappa u; the same structure at n=96 elementwise against the oracle
@@ -86,7 +87,7 @@ def test_c1_unblocked_dd_n64(mp, orc):
     xo, LUo, ipo, _ = orc.gesv(A, b)
     x, LU, ip, info, _ = gesv_gpu(mp, A, b, panel=n, method="4m")
     assert info == 0 and np.array_equal(ip, ipo)
-    kappa = float(np.real(np.linalg.cond(orc.hi_complex(A), np.inf)))
+    kappa = orc.cond_inf_est(A, LUo, ipo)
     assert fwd_err(x, xo, orc) <= 10 * n * kappa * U_FMT[C]
     assert np.abs(orc.diff(LU, LUo)).max() <= 100 * n * U_FMT[C] * np.abs(orc.hi_complex(LUo)).max()
     eta = orc.backward_error(A, x, b)
@@ -99,7 +100,10 @@ def test_c2_dd_n1024_3m_vs_4m(mp, orc):
     A = orc.canon(synthgen.uniform(n, n, C, 0))
     xt = synthgen.ones(n, 1, C)
     b = orc.matmul_exact(A, xt)
-    kappa = float(np.real(np.linalg.cond(orc.hi_complex(A), np.inf)))
+    # the oracle's own solution and its condition estimate (Hager / Higham on A^H)
+    xo, LUo, ipo, info_o = orc.gesv(A, b)
+    assert info_o == 0
+    kappa = orc.cond_inf_est(A, LUo, ipo)
     res = {}
     for method in ("3m", "4m"):
         gesv_gpu(mp, A, b, panel=64, method=method)  # warm-up
@@ -111,9 +115,11 @@ def test_c2_dd_n1024_3m_vs_4m(mp, orc):
         eta = float(np.abs(r).max() / (nA * nx))
         eta_im = float(np.abs(r.imag).max() / (nA * nx))
         fe = fwd_err(x, xt, orc)
-        res[method] = dict(eta=eta, eta_im=eta_im, fwd=fe, seconds=dt, x=x)
+        fo = fwd_err(x, xo, orc)
+        res[method] = dict(eta=eta, eta_im=eta_im, fwd=fe, fwd_vs_oracle=fo, seconds=dt, x=x)
         assert eta <= 10 * n * U_FMT[C]
         assert fe <= 10 * n * kappa * U_FMT[C]
+        assert fo <= 10 * n * kappa * U_FMT[C]
     agree = fwd_err(res["3m"]["x"], res["4m"]["x"], orc)
     assert agree <= 20 * n * kappa * U_FMT[C]
     record("C2", kappa=kappa, t3m_over_t4m=res["3m"]["seconds"] / res["4m"]["seconds"],
