@@ -82,6 +82,7 @@ typedef struct {
 #define MPLU_E_WORKSPACE (-100)   /* work_bytes below the *_wsbytes figure            */
 #define MPLU_E_HIP (-101)         /* a HIP runtime call or kernel launch failed       */
 #define MPLU_E_UNSUPPORTED (-102) /* size / option combination not supported          */
+#define MPLU_E_SCRATCH (-103)     /* mplu_zgesv_noalloc: workspace need above its scratch */
 
 /* Value written to *d_info when the panel's inter-workgroup barrier did not complete
  * within its bounded wait (the factors are then invalid). */
@@ -154,6 +155,29 @@ int mplu_zgesv_wsbytes(int prec, int64_t n, int64_t nrhs, const mplu_opts_t *opt
 int mplu_zgesv(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv,
                mplu_zmat_t B, int32_t *d_info, const mplu_opts_t *opts, void *d_work,
                size_t work_bytes, void *stream);
+
+/*
+ * mplu_zgesv_noalloc -- mplu_zgesv for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ *   Same arguments, results and d_info as mplu_zgesv (bitwise the same X, factors and
+ *   pivots), without d_work / work_bytes: the workspace is a static device array of
+ *   MPLU_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the process
+ *   ends and looked up on the first call on each device.  The call allocates nothing,
+ *   creates no stream or event, and runs every step in order on `stream` (the look-ahead
+ *   of mplu_zgetrf needs a second stream, so it is not used; MPLU_FLAG_NO_LOOKAHEAD is
+ *   implied).
+ *   Returns MPLU_E_SCRATCH, before enqueuing anything, when mplu_zgesv_wsbytes for these
+ *   sizes and options exceeds MPLU_NOALLOC_SCRATCH_BYTES (e.g. QD with panel 128 fits for
+ *   n*nrhs up to about 3.8e5 complex entries of B per call; the split methods' digit
+ *   planes fit only small n).
+ *   All calls on one GPU share its scratch array: calls that overlap in time on one GPU
+ *   (different streams or threads) race and must be serialised by the caller.  Each
+ *   call clears what it needs zeroed itself; nothing is carried between calls.
+ */
+#define MPLU_NOALLOC_SCRATCH_BYTES (16u << 20)
+int mplu_zgesv_noalloc(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv,
+                       mplu_zmat_t B, int32_t *d_info, const mplu_opts_t *opts,
+                       void *stream);
 
 /* mplu_zgemm_wsbytes -- workspace bytes mplu_zgemm needs (0 for 3M and 4M; the split
  * digit planes; for MPLU_GEMM_STRASSEN an m x n product and the two half-size operand

@@ -16,7 +16,8 @@ import os
 
 import torch
 
-__all__ = ["lib", "renorm_", "convert", "getrf", "getrs", "gesv", "gemm", "solve",
+__all__ = ["lib", "renorm_", "convert", "getrf", "getrs", "gesv", "gesv_noalloc", "gemm",
+           "solve",
            "lu_factor", "lu_solve",
            "dgetrf", "dgetrs", "dgesv", "dgemm",
            "GEMM_4M", "GEMM_3M", "GEMM_SPLIT_F64", "GEMM_SPLIT_I8", "GEMM_STRASSEN",
@@ -73,6 +74,8 @@ def lib():
     L.mplu_zgesv_wsbytes.argtypes = [ct.c_int, i64, i64, ct.POINTER(Opts), ct.POINTER(sz)]
     L.mplu_zgesv.argtypes = [ct.c_int, i64, i64, ZMat, i32p, ZMat, i32p, ct.POINTER(Opts), vp,
                              sz, vp]
+    L.mplu_zgesv_noalloc.argtypes = [ct.c_int, i64, i64, ZMat, i32p, ZMat, i32p,
+                                     ct.POINTER(Opts), vp]
     L.mplu_zgemm_wsbytes.argtypes = [ct.c_int, i64, i64, i64, ct.c_int, ct.POINTER(Opts),
                                      ct.POINTER(sz)]
     L.mplu_zgemm.argtypes = [ct.c_int, ct.c_char, ct.c_char, i64, i64, i64, ct.c_int, ZMat,
@@ -88,6 +91,7 @@ def lib():
                              DMat, ct.c_int, DMat, vp]
     for name in ("mplu_zrenorm", "mplu_zconvert", "mplu_zgetrf_wsbytes", "mplu_zgetrf",
                  "mplu_zgetrs_wsbytes", "mplu_zgetrs", "mplu_zgesv_wsbytes", "mplu_zgesv",
+                 "mplu_zgesv_noalloc",
                  "mplu_zgemm_wsbytes", "mplu_zgemm", "mplu_dgetrf_wsbytes", "mplu_dgetrf",
                  "mplu_dgetrs_wsbytes", "mplu_dgetrs", "mplu_dgesv_wsbytes", "mplu_dgesv",
                  "mplu_dgemm"):
@@ -193,6 +197,23 @@ def gesv(A: torch.Tensor, B: torch.Tensor, panel: int = 64, method="3m", n_slice
     info = torch.zeros(1, dtype=torch.int32, device=A.device)
     _check(lib().mplu_zgesv(C, n, nrhs, _zmat(A), ipiv.data_ptr(), _zmat(B), info.data_ptr(),
                             ct.byref(o), work.data_ptr(), work.numel(), _stream()), "mplu_zgesv")
+    return ipiv[:n], info
+
+
+def gesv_noalloc(A: torch.Tensor, B: torch.Tensor, panel: int = 64, method="3m",
+                 n_slices: int = 0, slice_bits: int = 0):
+    """gesv without a workspace argument: the library's static scratch stands in for it
+    (no device allocation by the library; the ipiv and info outputs are allocated here,
+    callers that cannot allocate call mplu_zgesv_noalloc with their own).  Every step
+    runs in order on the current stream.  Returns (ipiv, info)."""
+    C, n = A.shape[1], A.shape[2]
+    nrhs = B.shape[2]
+    o = _opts(panel, method, n_slices, slice_bits, True)
+    ipiv = torch.zeros(max(1, n), dtype=torch.int32, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(lib().mplu_zgesv_noalloc(C, n, nrhs, _zmat(A), ipiv.data_ptr(), _zmat(B),
+                                    info.data_ptr(), ct.byref(o), _stream()),
+           "mplu_zgesv_noalloc")
     return ipiv[:n], info
 
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "mplu.h"
@@ -254,6 +255,9 @@ const char *mplu_strerror(int code) {
     case MPLU_E_WORKSPACE: return "workspace too small";
     case MPLU_E_HIP: return "HIP runtime error or kernel launch failure";
     case MPLU_E_UNSUPPORTED: return "unsupported size or option combination";
+    case MPLU_E_SCRATCH:
+      return "workspace need exceeds the static scratch of mplu_zgesv_noalloc "
+             "(MPLU_NOALLOC_SCRATCH_BYTES)";
     default: break;
   }
   if (code < 0 && code > -20) return "invalid argument";
@@ -548,6 +552,64 @@ int mplu_zgesv(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv
   if (rc == -7) return -8;  // the options (the only argument not checked above)
   if (rc != 0) return rc;
   return mplu_zgetrs(prec, 'N', n, nrhs, A, d_ipiv, B, d_work, work_bytes, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ no-allocation gesv
+// mplu_zgesv_noalloc takes its workspace from this array instead of the caller.  Each
+// device holds its own copy at its own address, looked up once per device; host code
+// only ever hands kernels that address, never the array's name.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)MPLU_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::atomic<void *> g_scratch_ptr[kMaxDevices];
+
+// device address of the current device's scratch (nullptr if the lookup failed)
+void *scratch_ptr() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (p) return p;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+  if (p) return p;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return nullptr;
+  g_scratch_ptr[dev].store(p, std::memory_order_release);
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mplu_zgesv_noalloc(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv,
+                       mplu_zmat_t B, int32_t *d_info, const mplu_opts_t *opts,
+                       void *stream) {
+  if (!prec_ok(prec)) return -1;
+  if (n < 0) return -2;
+  if (nrhs < 0) return -3;
+  if (!mat_ok(A, n, n)) return -4;
+  if (n > 0 && d_ipiv == nullptr) return -5;
+  if (!mat_ok(B, n, nrhs)) return -6;
+  if (d_info == nullptr) return -7;
+  // every step in order on `stream`: the look-ahead's second stream and its events are
+  // left out, so nothing is created here
+  mplu_opts_t o = opts ? *opts : mplu_opts_t{0, MPLU_GEMM_3M, 0, 0, 0};
+  if (o.panel < 0 || (o.flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0) return -8;
+  o.flags |= MPLU_FLAG_NO_LOOKAHEAD;
+  size_t need = 0;
+  if (mplu_zgesv_wsbytes(prec, n, nrhs, &o, &need) != 0) return -8;
+  if (need > kScratchBytes) return MPLU_E_SCRATCH;
+  void *ws = scratch_ptr();
+  if (ws == nullptr) return MPLU_E_HIP;
+  int rc = getrf_core(prec, n, n, A, d_ipiv, d_info, &o, ws, kScratchBytes, stream, false);
+  if (rc == -7) return -8;
+  if (rc != 0) return rc;
+  return getrs_core(prec, 'N', n, nrhs, A, d_ipiv, B, ws, kScratchBytes, stream, false);
 }
 
 int mplu_zgemm_wsbytes(int prec, int64_t m, int64_t n, int64_t k, int method,

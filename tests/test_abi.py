@@ -111,6 +111,29 @@ def test_argument_checks(L):
     for pw, nn in ((256, 512), (129, 4096), (4096, 4096), (200, 200)):
         wide = m.Opts(pw, 1, 0, 0, 0)
         assert L.mplu_zgetrf(2, nn, nn, big, ip, inf, ct.byref(wide), wk, 1 << 40, None) == -102
+    # the no-allocation gesv: the same argument checks, and the static scratch limit,
+    # all decided before anything touches the GPU
+    assert L.mplu_zgesv_noalloc(5, 8, 1, z, ip, z, inf, None, None) == -1
+    assert L.mplu_zgesv_noalloc(2, -1, 1, z, ip, z, inf, None, None) == -2
+    assert L.mplu_zgesv_noalloc(2, 8, -1, z, ip, z, inf, None, None) == -3
+    assert L.mplu_zgesv_noalloc(2, 8, 1, null, ip, z, inf, None, None) == -4
+    assert L.mplu_zgesv_noalloc(2, 8, 1, z, None, z, inf, None, None) == -5
+    assert L.mplu_zgesv_noalloc(2, 8, 2, z, ip, m.ZMat(0x1000, 8, 8), inf, None, None) == -6
+    assert L.mplu_zgesv_noalloc(2, 8, 1, z, ip, z, None, None, None) == -7
+    assert L.mplu_zgesv_noalloc(2, 8, 1, z, ip, z, inf, ct.byref(bad), None) == -8
+    scratch = 16 << 20
+    sz = ct.c_size_t()
+    for C, n, nrhs, opt in ((4, 4096, 64, None), (2, 4096, 1, m.Opts(64, 3, 0, 0, 0)),
+                            (2, 8192, 200, None)):
+        assert L.mplu_zgesv_wsbytes(C, n, nrhs, ct.byref(opt) if opt else None,
+                                    ct.byref(sz)) == 0
+        assert sz.value > scratch
+        A = m.ZMat(0x1000, n, n * n)
+        Bm = m.ZMat(0x1000, n, n * nrhs)
+        rc = L.mplu_zgesv_noalloc(C, n, nrhs, A, ip, Bm, inf,
+                                  ct.byref(opt) if opt else None, None)
+        assert rc == -103, (C, n, nrhs, rc)
+    assert L.mplu_strerror(-103).startswith(b"workspace need exceeds the static scratch")
     assert L.mplu_zrenorm(2, 8, 8, null, None) == -4
     assert L.mplu_zconvert(2, 7, 8, 8, z, z, None) == -2
 
