@@ -12,8 +12,9 @@ step but not counted).  Besides the headline line, the JSON carries: the backwar
 of the last solve (exact-enough residual computed on the GPU in quadruple-double), the
 4M / triple-double / quadruple-double variants, the roofline of the dominant kernel (the
 3M trailing-update GEMM, timed live with HIP events), the complex matrix-product
-benchmark of Sec. 2.4 (C := A B, n = 2048, every product form), the real (Im = 0) gesv
-and the CPU oracle baseline.
+benchmark of Sec. 2.4 (C := A B, n = 2048, every product form), the first trailing update
+of the factorisation in every product form including Strassen-Winograd, the real (Im = 0)
+gesv and the CPU oracle baseline.
 `--panel-sweep 32,64,96,128` instead runs the panel-width sweep on the paper's LU workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 4096] [--panel 64]
@@ -193,7 +194,7 @@ def split_roofline(mp, torch, A0, panel, n_launch=12):
     base = M.data_ptr()
     stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
     S = 17
-    opts = mp._opts(panel, "split_i8")
+    opts = mp._gemm_opts("split_i8")
     nb = ct.c_size_t()
     r0 = n - panel
     assert L.mplu_zgemm_wsbytes(C, r0, r0, panel, 3, ct.byref(opts), ct.byref(nb)) == 0
@@ -278,6 +279,44 @@ def matmul_bench(mp, torch, synthgen, n, reps=3):
         torch.cuda.empty_cache()
     return {"n": n, "op": "C := A B, complex, leading components uniform[0,1]",
             "flops": "8 n^3 per product", "results": out}
+
+
+def update_forms(mp, torch, synthgen, n, K, reps=5):
+    """The first trailing update of the factorisation, A22 := A22 - L21 U12 with
+    m = n - K rows and columns and depth K, in every product form the update could use:
+    4M, 3M, split INT8, split FP64, and one level of Strassen-Winograd over 3M (Sec. 2.1;
+    the paper's Strassen LU of Table 1).  Mean of `reps` HIP-event-timed launches after a
+    warm-up; DD and QD."""
+    m = n - K
+    out = {}
+    for C in (2, 4):
+        L21 = torch.from_numpy(synthgen.uniform(m, K, C, 21)).cuda()
+        U12 = torch.from_numpy(synthgen.uniform(K, m, C, 22)).cuda()
+        A22 = torch.from_numpy(synthgen.uniform(m, m, C, 23)).cuda()
+        for T in (L21, U12, A22):
+            mp.renorm_(T)
+        for meth in ("4m", "3m", "split_i8", "split_f64", "strassen"):
+            times = []
+            for r in range(reps + 1):
+                T = A22.clone()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                mp.gemm(L21, U12, T, alpha=-1, method=meth)
+                e1.record()
+                torch.cuda.synchronize()
+                if r:
+                    times.append(e0.elapsed_time(e1))
+                del T
+            ms = sum(times) / len(times)
+            key = f"{['', '', 'DD', 'TD', 'QD'][C]}_{meth}"
+            out[key] = {"ms": round(ms, 4),
+                        "gflops": round(8.0 * m * m * K / (ms / 1e3) / 1e9, 2)}
+            print(f"[bench] update n={n} K={K} {key}: {out[key]}", file=sys.stderr, flush=True)
+        del L21, U12, A22
+        torch.cuda.empty_cache()
+    return {"m": m, "n": m, "k": K, "op": "A22 := A22 - L21 U12 (first trailing update)",
+            "flops": "8 m^2 k per update", "results": out}
 
 
 def panel_sweep(mp, torch, synthgen, n, panels, steps=2):
@@ -452,9 +491,14 @@ def main():
         print(f"[bench] split roofline {line['roofline_split_i8']}", file=sys.stderr, flush=True)
     if not args.no_variants:
         var = {}
-        runs = ((2, "4m", panel, 2), (2, "3m", 128, 2), (2, "split_i8", 128, 2),
-                (2, "split_i8", panel, 2), (2, "split_f64", 128, 1), (3, "3m", panel, 1),
-                (3, "split_i8", panel, 1), (4, "3m", panel, 1), (4, "split_i8", panel, 1))
+        # the metric's grid: DD / TD / QD x {4M, 3M, split INT8, split FP64}, panels 64
+        # and 128 (DD 3M at the headline's panel is the headline itself)
+        runs = ((2, "4m", panel, 2), (2, "3m", 128, 2), (2, "split_i8", panel, 2),
+                (2, "split_i8", 128, 2), (2, "split_f64", panel, 1), (2, "split_f64", 128, 1))
+        for C in (3, 4):
+            runs += ((C, "3m", panel, 1), (C, "3m", 128, 1), (C, "4m", panel, 1),
+                     (C, "split_i8", panel, 1), (C, "split_i8", 128, 1),
+                     (C, "split_f64", panel, 1))
         probs = {2: (A0, B0)}
         for (C, meth, pnl, steps) in runs:
             if C not in probs:
@@ -471,8 +515,14 @@ def main():
             torch.cuda.empty_cache()
         del probs
         line["variants"] = var
+        line["variants_eta"] = ("eta of every variant is formed by the library itself (a QD "
+                                "residual on the GPU): accurate far below the DD and TD "
+                                "working precisions, but itself at working precision for "
+                                "QD solutions; the exact-residual figures "
+                                "of the same grid are asserted by tests/test_gpu_fullsize.py")
     if not args.no_matmul:
         line["matmul"] = matmul_bench(mp, torch, synthgen, args.matmul_n)
+        line["update_forms"] = update_forms(mp, torch, synthgen, n, panel)
     if not args.no_variants:
         line["real"] = real_bench(mp, torch, synthgen, n, panel)
     if not args.no_cpu_baseline:

@@ -20,10 +20,12 @@
  *
  * CONVENTIONS SHARED BY ALL ENTRY POINTS
  *  - Pointers named d_* and every mplu_zmat_t.planes are DEVICE pointers (hipMalloc'd or
- *    from a caching allocator).  The caller owns all memory; the library never allocates
- *    device memory, frees or synchronises the host.  Work is enqueued on `stream` (a
- *    hipStream_t; NULL = default); mplu_zgetrf also forks part of it onto an internal
- *    stream and joins it back (see there).
+ *    from a caching allocator).  The caller owns all memory and streams; the library
+ *    never allocates device memory, frees or synchronises the host, and keeps no state
+ *    between calls other than cached device properties (and the static scratch of
+ *    mplu_zgesv_noalloc).  Work is enqueued on `stream` (a hipStream_t; NULL = default);
+ *    mplu_zgetrf also forks part of it onto the caller's opts->aux_stream, if given, and
+ *    joins it back (see there).
  *  - Return value (synchronous, decided before anything is enqueued): 0 on success,
  *    -i when argument i (1-based) is invalid, or one of the MPLU_E_* codes below.
  *  - Numerical failure is reported asynchronously through d_info (LAPACK getf2 rules).
@@ -71,11 +73,19 @@ typedef struct {
   int32_t n_slices;   /* split methods: slices per operand, 0 = automatic                   */
   int32_t slice_bits; /* split methods: bits per slice, 0 = automatic                       */
   int32_t flags;      /* MPLU_FLAG_* bits [0]                                               */
+  void *aux_stream;   /* mplu_zgetrf / mplu_zgesv: a second hipStream_t of the caller's on
+                         the same device, for the look-ahead described under mplu_zgetrf
+                         [NULL: no look-ahead, every step in order on `stream`]          */
 } mplu_opts_t;
 
 /* mplu_zgetrf / mplu_zgesv flag: run every step on `stream` in order, without the
- * look-ahead described under mplu_zgetrf.  The results are bitwise the same. */
+ * look-ahead, even when aux_stream is given.  The results are bitwise the same. */
 #define MPLU_FLAG_NO_LOOKAHEAD 1
+/* mplu_zgetrf / mplu_zgesv flag, for tests of the failure path only: the panel's bounded
+ * inter-workgroup waits start out expired, so each gives up at its first look at the
+ * expiry word (every kernel still ends normally); *d_info then reads
+ * MPLU_INFO_SYNC_TIMEOUT and the factors are not to be used. */
+#define MPLU_FLAG_EXPIRE_WAITS 2
 
 /* Error codes (besides -i for argument i). */
 #define MPLU_OK 0
@@ -112,12 +122,14 @@ int mplu_zgetrf_wsbytes(int prec, int64_t m, int64_t n, const mplu_opts_t *opts,
 /*
  * mplu_zgetrf -- P A = L U by blocked right-looking LU with partial pivoting (Sec. 3,
  * Fig. 8; "Normal LU" when opts->panel >= min(m, n)).
- *   Look-ahead: while panel k+1 is factored on `stream`, the step-k update of the
- *   columns right of panel k+1 runs on a second stream of the library (one per device,
- *   created on first use and kept until the process ends), forked from and joined back
- *   to `stream` with events, so the call still behaves as one ordered unit of work on
- *   `stream` (also under stream capture).  Concurrent calls on one device are serialised
- *   on that second stream.  MPLU_FLAG_NO_LOOKAHEAD keeps everything on `stream`.
+ *   Look-ahead (when opts->aux_stream is given): while panel k+1 is factored on
+ *   `stream`, the step-k update of the columns right of panel k+1 runs on aux_stream,
+ *   forked from and joined back to `stream` with three events that the call creates and
+ *   releases, so the call still behaves as one ordered unit of work on `stream` (also
+ *   under stream capture): aux_stream starts after the work already on `stream`, and
+ *   work enqueued on `stream` after the call starts after all of it.  Calls on different
+ *   caller streams with different aux streams proceed independently.  Without
+ *   aux_stream, or with MPLU_FLAG_NO_LOOKAHEAD, every step runs in order on `stream`.
  *   A (m x n) is overwritten by L (unit diagonal not stored) and U.
  *   d_ipiv: min(m,n) int32, 1-based row interchanges in LAPACK order (row k was swapped
  *           with row d_ipiv[k]-1, for k ascending).

@@ -45,7 +45,7 @@ class DMat(ct.Structure):
 
 class Opts(ct.Structure):
     _fields_ = [("panel", ct.c_int32), ("gemm", ct.c_int32), ("n_slices", ct.c_int32),
-                ("slice_bits", ct.c_int32), ("flags", ct.c_int32)]
+                ("slice_bits", ct.c_int32), ("flags", ct.c_int32), ("aux_stream", ct.c_void_p)]
 
 
 _lib = None
@@ -123,10 +123,33 @@ def _stream():
 FLAG_NO_LOOKAHEAD = 1
 
 
-def _opts(panel=64, method="3m", n_slices=0, slice_bits=0, lookahead=True) -> Opts:
+FLAG_EXPIRE_WAITS = 2
+
+# the look-ahead's second stream for each (device, caller stream): created by torch at the
+# default priority on first use and kept, like torch's own stream pool
+_aux_streams: dict = {}
+
+
+def _aux_stream():
+    cur = torch.cuda.current_stream()
+    key = (cur.device.index, cur.cuda_stream)
+    s = _aux_streams.get(key)
+    if s is None:
+        s = torch.cuda.Stream(device=cur.device)
+        _aux_streams[key] = s
+    return s.cuda_stream
+
+
+def _opts(panel=64, method="3m", n_slices=0, slice_bits=0, lookahead=True, flags=0) -> Opts:
     m = _METHODS[method] if isinstance(method, str) else int(method)
     return Opts(int(panel), m, int(n_slices), int(slice_bits),
-                0 if lookahead else FLAG_NO_LOOKAHEAD)
+                int(flags) | (0 if lookahead else FLAG_NO_LOOKAHEAD),
+                _aux_stream() if lookahead else None)
+
+
+def _gemm_opts(method="3m", n_slices=0, slice_bits=0) -> Opts:
+    m = _METHODS[method] if isinstance(method, str) else int(method)
+    return Opts(64, m, int(n_slices), int(slice_bits), 0, None)
 
 
 def _work(nbytes: int, device) -> torch.Tensor:
@@ -208,7 +231,7 @@ def gesv_noalloc(A: torch.Tensor, B: torch.Tensor, panel: int = 64, method="3m",
     runs in order on the current stream.  Returns (ipiv, info)."""
     C, n = A.shape[1], A.shape[2]
     nrhs = B.shape[2]
-    o = _opts(panel, method, n_slices, slice_bits, True)
+    o = _opts(panel, method, n_slices, slice_bits, lookahead=False)
     ipiv = torch.zeros(max(1, n), dtype=torch.int32, device=A.device)
     info = torch.zeros(1, dtype=torch.int32, device=A.device)
     _check(lib().mplu_zgesv_noalloc(C, n, nrhs, _zmat(A), ipiv.data_ptr(), _zmat(B),
@@ -234,7 +257,7 @@ def gemm(A: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor | None = None, opA: 
         beta = 0
         Cm = torch.empty((2, C, n, m), dtype=torch.float64, device=A.device)
     meth = _METHODS[method] if isinstance(method, str) else int(method)
-    o = _opts(64, meth, n_slices, slice_bits)
+    o = _gemm_opts(meth, n_slices, slice_bits)
     nb = ct.c_size_t()
     _check(lib().mplu_zgemm_wsbytes(C, m, n, k, meth, ct.byref(o), ct.byref(nb)), "wsbytes")
     work = _work(nb.value, A.device)

@@ -1,7 +1,8 @@
 // capi.cpp -- the exported C ABI (declared in include/mplu.h): argument checks, workspace
 // layout and the host-side loops of the blocked LU (Kouya Sec. 3, Fig. 8) and of the
 // forward / backward substitutions (Sec. 4).  All work is enqueued on the caller's
-// stream; nothing here allocates, frees or synchronises.
+// stream (and, for the factorisation's look-ahead, on the second stream the caller
+// passes in the options); nothing here allocates device memory, frees or synchronises.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -109,31 +110,23 @@ int getrf_ws(int C, int64_t m, int64_t n, const mplu_opts_t *o, size_t *bytes) {
   return 0;
 }
 
-// The library's second stream on the current device, with the two events that order it
-// against the caller's stream.  Created on first use and kept for the process lifetime;
-// the returned lock serialises the enqueue sequences that use them.
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t ev_panel = nullptr, ev_rest = nullptr, ev_chain = nullptr;
-  bool ready = false;
-};
-constexpr int kMaxDevices = 64;
-std::mutex g_side_mu;
-SideStream g_side[kMaxDevices];
-
-SideStream *side_stream() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-  SideStream &sd = g_side[dev];
-  if (!sd.ready) {
-    if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&sd.ev_panel, hipEventDisableTiming) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&sd.ev_rest, hipEventDisableTiming) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&sd.ev_chain, hipEventDisableTiming) != hipSuccess) return nullptr;
-    sd.ready = true;
+// The look-ahead's ordering events: created per call (they are tied to the caller's two
+// streams, which may change from call to call) and released at its end; a release while
+// work that records or waits on them is still queued takes effect once that work is done.
+struct LookaheadEvents {
+  hipEvent_t panel = nullptr, rest = nullptr, chain = nullptr;
+  hipError_t create() {
+    hipError_t e;
+    if ((e = hipEventCreateWithFlags(&panel, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&rest, hipEventDisableTiming)) != hipSuccess) return e;
+    return hipEventCreateWithFlags(&chain, hipEventDisableTiming);
   }
-  return &sd;
-}
+  ~LookaheadEvents() {
+    if (panel) (void)hipEventDestroy(panel);
+    if (rest) (void)hipEventDestroy(rest);
+    if (chain) (void)hipEventDestroy(chain);
+  }
+};
 
 // the trailing update of one step restricted to columns [c0, c1): U12 := L11^-1 A12 on
 // those columns, then A22 -= L21 U12 on them
@@ -247,7 +240,7 @@ hipError_t strassen_zgemm(int C, int64_t m, int64_t n, int64_t k, int alpha, ZM 
 
 extern "C" {
 
-int mplu_version(void) { return 10000; }
+int mplu_version(void) { return 10100; }
 
 const char *mplu_strerror(int code) {
   switch (code) {
@@ -310,7 +303,9 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   const int64_t mn = m < n ? m : n;
   if (mn > 0 && d_ipiv == nullptr) return -5;
   if (d_info == nullptr) return -6;
-  if (opts && (opts->panel < 0 || (opts->flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0)) return -7;
+  if (opts && (opts->panel < 0 ||
+               (opts->flags & ~(MPLU_FLAG_NO_LOOKAHEAD | MPLU_FLAG_EXPIRE_WAITS)) != 0))
+    return -7;
   const int method = gemm_method(opts);
   if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M && method != MPLU_GEMM_SPLIT_F64 &&
       method != MPLU_GEMM_SPLIT_I8)
@@ -346,8 +341,10 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   const int S = opts ? opts->n_slices : 0;
 
   unsigned base[3] = {0u, 0u, 0u};
-  for (int i = 0; i < 3; ++i) HIPCHK(panel_ws_clear(pws[i], s));
-  if (opts && (opts->flags & MPLU_FLAG_NO_LOOKAHEAD)) {
+  const bool expire = opts && (opts->flags & MPLU_FLAG_EXPIRE_WAITS);
+  for (int i = 0; i < 3; ++i) HIPCHK(panel_ws_clear(pws[i], expire, s));
+  const hipStream_t b = opts ? (hipStream_t)opts->aux_stream : nullptr;
+  if (b == nullptr || b == s || (opts->flags & MPLU_FLAG_NO_LOOKAHEAD)) {
     for (int64_t j = 0; j < mn; j += kb) {
       const int jb = (int)((mn - j) < kb ? (mn - j) : kb);
       HIPCHK(launch_panel(C, a, j, m, jb, d_ipiv, d_info, pws[0], &base[0], s, real));
@@ -358,17 +355,17 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
   }
 
   // Look-ahead by one panel.  After panel k (columns [j, j+jb)) is factored:
-  //   caller's stream:  interchanges, U12 and A22 update of the next panel's columns,
+  //   stream `s`:       interchanges, U12 and A22 update of the next panel's columns,
   //                     then panel k+1;
-  //   second stream:    interchanges and U12 of the columns right of the next panel, their
+  //   second stream b:  interchanges and U12 of the columns right of the next panel, their
   //                     A22 update, then the interchanges of the columns left of panel k
   //                     (nothing reads those before the end).
   // The next panel's columns are up to date through step k-1 only after the second
-  // stream's step k-1 product, which the caller's stream waits for first.
-  std::lock_guard<std::mutex> lock(g_side_mu);
-  SideStream *sd = side_stream();
-  if (!sd) return MPLU_E_HIP;
-  const hipStream_t b = sd->s;
+  // stream's step k-1 product, which `s` waits for first.  b first waits for everything
+  // enqueued on `s` before this call (the event recorded before panel 0), and `s` waits
+  // for all of b's work at the end, so the call is one ordered unit of work on `s`.
+  LookaheadEvents ev;
+  HIPCHK(ev.create());
   HIPCHK(launch_panel(C, a, 0, m, (int)(mn < kb ? mn : kb), d_ipiv, d_info, pws[0], &base[0], s,
                       real));
   int k = 0;
@@ -377,9 +374,9 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     void *pw = pws[k % 3];
     const int64_t nx0 = j + jb;  // next panel's columns [nx0, nx1)
     const int64_t nx1 = nx0 < mn ? nx0 + ((mn - nx0) < kb ? (mn - nx0) : kb) : nx0;
-    HIPCHK(hipEventRecord(sd->ev_panel, s));
-    if (k > 0) HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));
-    HIPCHK(hipStreamWaitEvent(b, sd->ev_panel, 0));
+    HIPCHK(hipEventRecord(ev.panel, s));
+    if (k > 0) HIPCHK(hipStreamWaitEvent(s, ev.rest, 0));
+    HIPCHK(hipStreamWaitEvent(b, ev.panel, 0));
     if (nx1 > nx0) {
       // the next panel's columns: interchanges and U12 in one launch, then the product
       HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb), real));
@@ -387,11 +384,11 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     }
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device
-    HIPCHK(hipEventRecord(sd->ev_chain, s));
+    HIPCHK(hipEventRecord(ev.chain, s));
     HIPCHK(step_trsm(C, a, j, jb, nx1, n, b, panel_swap_list(pw, C, jb), real));
-    HIPCHK(hipStreamWaitEvent(b, sd->ev_chain, 0));
+    HIPCHK(hipStreamWaitEvent(b, ev.chain, 0));
     HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx1, n, split_rest, b, real));
-    HIPCHK(hipEventRecord(sd->ev_rest, b));
+    HIPCHK(hipEventRecord(ev.rest, b));
     // panel k's interchanges on the columns left of it; the workspace holding the list is
     // next written by panel k+3, which the caller's stream starts only after the second
     // stream's step k+1 product
@@ -400,8 +397,8 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
       HIPCHK(launch_panel(C, a, nx0, m, (int)(nx1 - nx0), d_ipiv, d_info, pws[(k + 1) % 3],
                           &base[(k + 1) % 3], s, real));
   }
-  HIPCHK(hipEventRecord(sd->ev_rest, b));
-  HIPCHK(hipStreamWaitEvent(s, sd->ev_rest, 0));
+  HIPCHK(hipEventRecord(ev.rest, b));
+  HIPCHK(hipStreamWaitEvent(s, ev.rest, 0));
   return 0;
 }
 
@@ -563,6 +560,7 @@ int mplu_zgesv(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t *d_ipiv
 namespace {
 
 constexpr size_t kScratchBytes = (size_t)MPLU_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 std::mutex g_scratch_mu;
@@ -598,9 +596,11 @@ int mplu_zgesv_noalloc(int prec, int64_t n, int64_t nrhs, mplu_zmat_t A, int32_t
   if (d_info == nullptr) return -7;
   // every step in order on `stream`: the look-ahead's second stream and its events are
   // left out, so nothing is created here
-  mplu_opts_t o = opts ? *opts : mplu_opts_t{0, MPLU_GEMM_3M, 0, 0, 0};
-  if (o.panel < 0 || (o.flags & ~MPLU_FLAG_NO_LOOKAHEAD) != 0) return -8;
+  mplu_opts_t o = opts ? *opts : mplu_opts_t{0, MPLU_GEMM_3M, 0, 0, 0, nullptr};
+  if (o.panel < 0 || (o.flags & ~(MPLU_FLAG_NO_LOOKAHEAD | MPLU_FLAG_EXPIRE_WAITS)) != 0)
+    return -8;
   o.flags |= MPLU_FLAG_NO_LOOKAHEAD;
+  o.aux_stream = nullptr;
   size_t need = 0;
   if (mplu_zgesv_wsbytes(prec, n, nrhs, &o, &need) != 0) return -8;
   if (need > kScratchBytes) return MPLU_E_SCRATCH;

@@ -112,8 +112,9 @@ PanelGeom panel_geometry(int C, int64_t mp, int kb);
 size_t panel_ws_bytes(int C, int kb);
 
 // clear the barrier words of a panel workspace (once per factorisation, before its
-// first panel)
-hipError_t panel_ws_clear(void *ws, hipStream_t s);
+// first panel); expire = true marks its bounded waits as expired (a test of the
+// time-out path, forced from the host)
+hipError_t panel_ws_clear(void *ws, bool expire, hipStream_t s);
 // factor rows [j, m) x columns [j, j+kb) in place; writes ipiv[j..j+kb), info, and the
 // swap list for the other columns into the workspace.  *base: barrier arrivals already
 // counted on this workspace since it was cleared; advanced past this panel's.

@@ -784,8 +784,12 @@ static hipError_t launch_panel_t(ZM A, int64_t j, int64_t m, int kb, int32_t *ip
   return hipGetLastError();
 }
 
-hipError_t panel_ws_clear(void *ws, hipStream_t s) {
-  return launch_fill_i32((int32_t *)ws, 0, 4, s);
+hipError_t panel_ws_clear(void *ws, bool expire, hipStream_t s) {
+  hipError_t e = launch_fill_i32((int32_t *)ws, 0, 4, s);
+  if (e != hipSuccess || !expire) return e;
+  // the expiry word set before the first wait: every bounded wait gives up at its first
+  // look at it and the panel reports MPLU_SYNC_TIMEOUT
+  return launch_fill_i32((int32_t *)ws + 2, 1, 1, s);
 }
 
 hipError_t launch_panel(int C, ZM A, int64_t j, int64_t m, int kb, int32_t *ipiv,

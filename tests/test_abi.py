@@ -56,14 +56,21 @@ def test_argument_checks(L):
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
     bad = m.Opts(64, 9, 0, 0, 0)
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
-    # flags: only MPLU_FLAG_NO_LOOKAHEAD (1) is defined
-    for flags in (2, 4, 1 | 8, -1):
+    # flags: only MPLU_FLAG_NO_LOOKAHEAD (1) and MPLU_FLAG_EXPIRE_WAITS (2) are defined
+    for flags in (4, 1 | 8, 2 | 16, -1):
         bad = m.Opts(64, 1, 0, 0, flags)
         assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(bad), wk, 1 << 30, None) == -7
         assert L.mplu_zgesv(2, 8, 1, z, ip, z, inf, ct.byref(bad), wk, 1 << 30, None) == -8
-    assert m.FLAG_NO_LOOKAHEAD == 1
-    assert re.search(r"#define\s+MPLU_FLAG_NO_LOOKAHEAD\s+1\b",
-                     open(os.path.join(ROOT, "include", "mplu.h")).read())
+    assert m.FLAG_NO_LOOKAHEAD == 1 and m.FLAG_EXPIRE_WAITS == 2
+    hdr = open(os.path.join(ROOT, "include", "mplu.h")).read()
+    assert re.search(r"#define\s+MPLU_FLAG_NO_LOOKAHEAD\s+1\b", hdr)
+    assert re.search(r"#define\s+MPLU_FLAG_EXPIRE_WAITS\s+2\b", hdr)
+    # the options structure as the header declares it (the binding's copy must match)
+    fields = re.search(r"typedef struct \{\s*int32_t panel;(.*?)\} mplu_opts_t;", hdr, re.S)
+    names = re.findall(r"^\s*(?:int32_t|void \*)\s*(\w+);", "int32_t panel;" + fields.group(1),
+                       re.M)
+    assert names == [f[0] for f in m.Opts._fields_]
+    assert ct.sizeof(m.Opts) == 32
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, None, ct.c_void_p(0x10001), 1 << 30, None) == -8
     assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, None, wk, 16, None) == -100
     assert L.mplu_zgetrs(2, b"X", 8, 1, z, ip, z, wk, 1 << 30, None) == -2

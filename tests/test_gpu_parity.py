@@ -437,8 +437,9 @@ def test_lookahead_repeated_calls_and_gesv(mp, orc):
 
 
 def test_lookahead_two_streams_concurrently(mp, orc):
-    """Two factorisations enqueued back to back on two different caller streams share the
-    library's second stream; each must still equal its in-order result."""
+    """Two factorisations enqueued back to back on two different caller streams (each
+    with its own second stream) run concurrently; each must still equal its in-order
+    result."""
     import torch
 
     n, C = 300, 2
@@ -595,3 +596,39 @@ def test_strassen_empty_and_k0(mp, orc):
     E = torch.zeros((2, C, 3, 0), dtype=torch.float64, device="cuda")
     F = torch.zeros((2, C, 0, 3), dtype=torch.float64, device="cuda")
     assert mp.gemm(E, F, None, m=0, method="strassen").numel() == 0
+
+
+@pytest.mark.parametrize("lookahead", [False, True])
+def test_expired_waits_report_timeout(mp, orc, lookahead):
+    """The panel's bounded waits, forced expired from the host (MPLU_FLAG_EXPIRE_WAITS),
+    give up and every kernel ends: the call completes with info = MPLU_INFO_SYNC_TIMEOUT.
+    The next ordinary call on the same workspace is unaffected (bit for bit the
+    reference factorisation)."""
+    import ctypes as ct
+
+    import torch
+
+    n, C = 300, 2
+    A = orc.canon(synthgen.uniform(n, n, C, 120))
+    T = to_dev(A)
+    ref_ip, ref_info = mp.getrf(T, panel=64, method="3m", lookahead=False)
+    sync()
+    ref = to_host(T)
+    o = mp._opts(64, "3m", lookahead=lookahead, flags=mp.FLAG_EXPIRE_WAITS)
+    nb = ct.c_size_t()
+    assert mp.lib().mplu_zgetrf_wsbytes(C, n, n, ct.byref(o), ct.byref(nb)) == 0
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    ipiv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    T = to_dev(A)
+    rc = mp.lib().mplu_zgetrf(C, n, n, mp._zmat(T), ipiv.data_ptr(), info.data_ptr(),
+                              ct.byref(o), work.data_ptr(), work.numel(), mp._stream())
+    assert rc == 0
+    sync()
+    assert int(info.item()) == -9999
+    T = to_dev(A)
+    ipiv2, info2 = mp.getrf(T, panel=64, method="3m", lookahead=lookahead, work=work)
+    sync()
+    assert int(info2.item()) == 0
+    assert np.array_equal(ipiv2.cpu().numpy(), ref_ip.cpu().numpy())
+    assert np.array_equal(to_host(T), ref)
