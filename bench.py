@@ -522,7 +522,8 @@ def main():
                                 "of the same grid are asserted by tests/test_gpu_fullsize.py")
     if not args.no_matmul:
         line["matmul"] = matmul_bench(mp, torch, synthgen, args.matmul_n)
-        line["update_forms"] = update_forms(mp, torch, synthgen, n, panel)
+        line["update_forms"] = [update_forms(mp, torch, synthgen, n, K)
+                                for K in sorted({panel, 128})]
     if not args.no_variants:
         line["real"] = real_bench(mp, torch, synthgen, n, panel)
     if not args.no_cpu_baseline:
