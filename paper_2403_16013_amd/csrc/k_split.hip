@@ -3,8 +3,9 @@
 // product of Eq. 3m_cemm:  Cm := beta Cm + alpha (T1 - T2) + i alpha (T3 - T1 - T2) with
 // T1 = ReX ReY, T2 = ImX ImY, T3 = (ReX + ImX)(ReY + ImY).
 //
-// Slicing: every vector v of a real operand (a row of op(A) or a column of op(B)) gets an
-// exponent tau_v with |x| < 2^(tau_v - 1) for all its entries, and each entry is written
+// Slicing: every vector v of an operand (a row of op(A) or a column of op(B)) gets one
+// exponent tau_v with |x| < 2^(tau_v - 1) for all its entries (real part, imaginary part
+// and their rounded sum alike), and each entry is written
 // as sum_{p=1..S} d_p 2^(tau_v - p W) + (dropped tail) with integer digits
 // |d_p| <= 2^(W-1) + 1, taken by round-to-nearest from the multi-component residual.
 // Digit products are exact: for INT8 (W = 7) the MFMA accumulates them exactly in INT32;
@@ -80,12 +81,17 @@ __global__ __launch_bounds__(256) void k_slice(SliceArgs a) {
 #pragma unroll
     for (int o = 0; o < NO; ++o) mx[o] = fmax(mx[o], fabs(x[o][0]));
   }
+  // one exponent for the vector's three operand sets (Re, Im, Re + Im): their digits then
+  // sit on one grid, so the three level sums of a product carry the same weights and
+  // combine exactly in integers (k_split_i8); it bounds each set's entries as well
+  double m = 0.0;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) m = fmax(m, wave_max(mx[o]));
+  int e = 0;
+  if (m > 0.0) frexp(m, &e);  // m < 2^e, hence every entry (with its tail) < 2^e
   int tau[3];
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    const double m = wave_max(mx[o]);
-    int e = 0;
-    if (m > 0.0) frexp(m, &e);  // m < 2^e, hence every entry (with its tail) < 2^e
     tau[o] = m > 0.0 ? e + 1 : 0;
     if (lane == 0) a.tau[o * a.nvec + v] = tau[o];
   }
@@ -207,15 +213,13 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
 
   // the exponent sums of this lane's four outputs for the three products, fetched up
   // front so the per-product flush does not wait on memory
-  int tsums[3][4];
+  // (one exponent per row / column serves all three products)
+  int tsums[4];
 #pragma unroll
-  for (int op = 0; op < NO; ++op)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
-      tsums[op][e] = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
-                     (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
-    }
+  for (int e = 0; e < 4; ++e) {
+    const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
+    tsums[e] = (mi < g.m ? g.tx[mi] : 0) + (nj < g.n ? g.ty[nj] : 0);
+  }
   const int nck = (int)(g.Kpad / 64);
   // piece e = (plane p, row r, quarter f) of chunk `it` (product it / nck)
   auto issue = [&](int it) {
@@ -237,13 +241,23 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
           (__attribute__((address_space(3))) void *)(dY + e0), 16, 0, 0);
     }
   };
-  for (int op = 0; op < NO; ++op) {
-    double sr, si;
-    op_signs(op, sr, si);
-    if (RE) si = 0.0;  // a real product has no imaginary part
-    v4i acc[S];
+  // Level l (0-based) of a product carries weight 2^(tau_i + tau_j - (l + 2) W), the same
+  // for the three products of Eq. 3m_cemm (one exponent per row / column for all three),
+  // so they combine exactly in INT32 in one set of level accumulators: after T1, twice
+  // T1 goes to the real part; T2 is added and the sum negated, -T1 - T2 goes to the real
+  // part too (which now holds T1 - T2) and is where the accumulation of T3 starts, which
+  // leaves I = T3 - T1 - T2 for the imaginary part.  Three flushes instead of five.
+  // Four consecutive levels span at most 26 + 3 W bits (|sum| < 3 x 64 S 65^2 per chunk,
+  // below 2^31 by the depth limit), so their scaled sum is exact in binary64.  A group
+  // starting at level lo is at most 2^(-lo W) of the largest possible level-0 sum, so for
+  // TD and QD it enters the accumulator at component level lo W / 53: the TwoSum steps
+  // above that level would only pass it down unchanged.  (For DD the saving is one
+  // TwoSum per group, and the shorter code needed more VGPRs than two waves per SIMD
+  // allow.)
+  v4i acc[S];
 #pragma unroll
-    for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
+  for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
+  for (int op = 0; op < NO; ++op) {
     for (int c = 0; c < nck; ++c) {
       issue(op * nck + c);
       __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces of the chunk have landed
@@ -262,18 +276,17 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
           acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
       __syncthreads();  // the buffer is refilled next
     }
-    // level l (0-based) carries weight 2^(tau_i + tau_j - (l + 2) W); four consecutive
-    // levels span at most 24 + 3 W bits, so their scaled sum is exact in binary64.  A
-    // group starting at level lo is at most 2^(-lo W) of the largest possible level-0
-    // sum, so for TD and QD it enters the accumulator at component level lo W / 53: the
-    // TwoSum steps above that level would only pass it down unchanged.  (For DD the
-    // saving is one TwoSum per group, and the shorter code needed 326 instead of 216
-    // VGPRs, which halved the waves per SIMD.)
+    if (!RE && op == 1) {
+#pragma unroll
+      for (int l = 0; l < S; ++l) acc[l] = -acc[l];  // -T1 - T2
+    }
+    // where the levels go: op 0 twice to the real part (a real product: once), op 1 to
+    // the real part, op 2 to the imaginary part
+    const int sc = (!RE && op == 0) ? 1 : 0;  // power of two
+    const bool to_re = RE || op < 2;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      int tsum = tsums[0][e];
-#pragma unroll
-      for (int o = 1; o < NO; ++o) tsum = (op == o) ? tsums[o][e] : tsum;
+      const int tsum = tsums[e] + sc;
 #pragma unroll
       for (int top = S - 1; top >= 0; top -= 4) {
         const int lo = top - 3 < 0 ? 0 : top - 3;
@@ -283,8 +296,8 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
         for (int l = top; l >= lo; --l)
           grp = __builtin_fma((double)acc[l][e], ldexp(1.0, (lo - l) * W), grp);
         grp = ldexp(grp, tsum - (lo + 2) * W);
-        if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * grp);
-        if (!RE) mp::push<C>(li[e], lvl, si * grp);
+        if (to_re) mp::push<C>(lr[e], lvl, grp);
+        else mp::push<C>(li[e], lvl, grp);
       }
     }
   }
@@ -367,10 +380,11 @@ static inline int64_t kpad_of(int64_t K, bool i8) {
 }
 
 // Depth of one INT8 split product.  A level sum of k_split_i8 gains at most 64 S 65^2 per
-// 64-deep chunk (S digit pairs of at most 65 x 65 at the top level), so it stays below
-// 2^31 for floor((2^31 - 1) / (64 S 65^2)) chunks: 467 (DD), 330 (TD), 248 (QD), i.e.
-// k up to 29 888, 21 120, 15 872.
-static int64_t split_i8_max_k(int S) { return (2147483647ll / (64ll * S * 65 * 65)) * 64; }
+// 64-deep chunk (S digit pairs of at most 65 x 65 at the top level), and the combined
+// sums of the complex product (T1 - T2, T3 - T1 - T2) up to three times that, so they stay
+// below 2^31 for floor((2^31 - 1) / (3 x 64 S 65^2)) chunks: 155 (DD), 110 (TD), 82 (QD),
+// i.e. k up to 9 920, 7 040, 5 248.
+static int64_t split_i8_max_k(int S) { return (2147483647ll / (3ll * 64 * S * 65 * 65)) * 64; }
 
 size_t split_ws_bytes(int C, bool i8, int64_t m, int64_t n, int64_t K, int S) {
   if (S <= 0) S = split_slices(C, i8);

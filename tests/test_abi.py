@@ -162,14 +162,15 @@ def test_workspace_queries(L):
     g = ct.c_size_t()
     assert L.mplu_zgemm_wsbytes(2, 4096, 4096, 128, 3, ct.byref(o3), ct.byref(g)) == 0
     assert i8 >= g.value
-    # INT8 split products deeper than the INT32 limit of a level sum (15 872 for QD) run in
-    # pieces of that depth, so their workspace stops growing there
+    # INT8 split products deeper than the INT32 limit of a combined level sum (5 248 for
+    # QD: three times 64 S 65^2 per 64-deep chunk below 2^31) run in pieces of that depth,
+    # so their workspace stops growing there
     deep, piece = ct.c_size_t(), ct.c_size_t()
     assert L.mplu_zgemm_wsbytes(4, 64, 64, 40000, 3, None, ct.byref(deep)) == 0
-    assert L.mplu_zgemm_wsbytes(4, 64, 64, 15872, 3, None, ct.byref(piece)) == 0
+    assert L.mplu_zgemm_wsbytes(4, 64, 64, 5248, 3, None, ct.byref(piece)) == 0
     assert deep.value == piece.value
-    assert L.mplu_zgemm_wsbytes(4, 64, 64, 15936, 3, None, ct.byref(deep)) == 0
-    assert L.mplu_zgemm_wsbytes(4, 64, 64, 15808, 3, None, ct.byref(g)) == 0
+    assert L.mplu_zgemm_wsbytes(4, 64, 64, 5312, 3, None, ct.byref(deep)) == 0
+    assert L.mplu_zgemm_wsbytes(4, 64, 64, 5184, 3, None, ct.byref(g)) == 0
     assert g.value < piece.value
     assert L.mplu_zgetrs_wsbytes(2, 100, 3, ct.byref(sz)) == 0
     assert sz.value >= 100 * 3 * 4 * 8

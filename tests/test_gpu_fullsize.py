@@ -145,3 +145,27 @@ def test_adjoint_vs_oracle_gradient(mp, orc, n, nrhs):
     print(f"n={n} nrhs={nrhs} kappa={kappa:.2e}: g_b {eb:.2e}, g_A {eA:.2e}")
     assert eb <= 10 * n * kappa * u
     assert eA <= 20 * n * kappa * u
+
+
+@pytest.mark.parametrize("C,k", [(4, 5248 + 203), (2, 9920 + 77)])
+def test_deep_split_i8_product_in_pieces(mp, orc, C, k):
+    """INT8 split products deeper than the INT32 limit of a combined level sum (three
+    times 64 S 65^2 per 64-deep chunk below 2^31: k = 5 248 for QD, 9 920 for DD) run as
+    consecutive pieces accumulated into the result: elementwise against the oracle within
+    the product bound, the slicing term and one rounding of the running sum per piece."""
+    m, n = 37, 29
+    A = orc.canon(synthgen.uniform(m, k, C, 40))
+    B = orc.canon(synthgen.uniform(k, n, C, 41))
+    Cm = orc.canon(synthgen.uniform(m, n, C, 42))
+    ref = orc.gemm(A, B, Cm, method=3, alpha_sign=-1)
+    Td = to_dev(Cm)
+    mp.gemm(to_dev(A), to_dev(B), Td, alpha=-1, method="split_i8")
+    got = to_host(Td)
+    a = (np.abs(A[0, 0]) + np.abs(A[1, 0])).T
+    b = (np.abs(B[0, 0]) + np.abs(B[1, 0])).T
+    S = a @ b + (np.abs(Cm[0, 0]) + np.abs(Cm[1, 0])).T
+    slicing = 16 * k * 2.0 ** (-53 * C - 2) * np.outer(a.max(axis=1), b.max(axis=0))
+    tol = 4 * (k + 4) * U_FMT[C] * S + slicing + 4 * U_FMT[C] * S
+    d = orc.diff(got, ref)
+    assert np.all(np.abs(d.real) <= tol) and np.all(np.abs(d.imag) <= tol)
+    print(f"C={C} k={k}: err / sum|a||b| {float(np.max(np.abs(d) / S)):.3e}")
