@@ -177,6 +177,89 @@ __device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t
   st_z<C>(g.Cm, g.ci + mi, g.cj + nj, orr, oi);
 }
 
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+
+// rows i .. i+3 of column j in each of the NQ planes of M, the first nv of them (a lane of
+// a 16 x 16 MFMA block holds four consecutive rows of one column): two 16-byte loads per
+// plane when all four are inside, else one element at a time; absent rows read as zero
+template <int NQ>
+__device__ __forceinline__ void ld_col4(const ZM &M, int64_t i, int64_t j, int nv,
+                                        double (&v)[NQ][4]) {
+  const double *b = M.p + j * M.ld + i;
+  if (nv == 4) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const d2u lo = *(const d2u *)(b + (int64_t)q * M.ps);
+      const d2u hi = *(const d2u *)(b + (int64_t)q * M.ps + 2);
+      v[q][0] = lo.x; v[q][1] = lo.y; v[q][2] = hi.x; v[q][3] = hi.y;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[q][e] = e < nv ? b[(int64_t)q * M.ps + e] : 0.0;
+  }
+}
+
+template <int NQ>
+__device__ __forceinline__ void st_col4(const ZM &M, int64_t i, int64_t j, int nv,
+                                        const double (&v)[NQ][4]) {
+  double *b = M.p + j * M.ld + i;
+  if (nv == 4) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      *(d2u *)(b + (int64_t)q * M.ps) = d2u{v[q][0], v[q][1]};
+      *(d2u *)(b + (int64_t)q * M.ps + 2) = d2u{v[q][2], v[q][3]};
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e < nv) b[(int64_t)q * M.ps + e] = v[q][e];
+  }
+}
+
+// epilogue of the four outputs (rows i .. i+3 of column j) of one lane, with the values
+// of C they update already in registers (cv, planes of the real then the imaginary part)
+template <int C, bool RE>
+__device__ __forceinline__ void epilogue4(const SplitArgs &g, int64_t i, int64_t j, int nv,
+                                          double (&lr)[4][C], double (&li)[4][C],
+                                          const double (&cv)[RE ? C : 2 * C][4]) {
+  if (nv == 0) return;
+  constexpr int NQ = RE ? C : 2 * C;
+  double out[NQ][4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (g.alpha < 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) { lr[e][c] = -lr[e][c]; li[e][c] = -li[e][c]; }
+    }
+    if (g.beta) {
+      double cr[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) cr[c] = cv[c][e];
+      mp::push_mp<C>(lr[e], cr);
+      if (!RE) {
+        double cim[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) cim[c] = cv[(RE ? 0 : C) + c][e];
+        mp::push_mp<C>(li[e], cim);
+      }
+    }
+    double o[C];
+    mp::renorm<C>(lr[e], o);
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[c][e] = o[c];
+    if (!RE) {
+      mp::renorm<C>(li[e], o);
+#pragma unroll
+      for (int c = 0; c < C; ++c) out[(RE ? 0 : C) + c][e] = o[c];
+    }
+  }
+  st_col4<NQ>(g.Cm, g.ci + i, g.cj + j, nv, out);
+}
+
 // INT8 digits, W = 7.  Workgroup: 4 waves, a 32 x 32 output tile; each wave a 16 x 16
 // block.  For each real product and each 64-deep k chunk the workgroup stages the S digit
 // planes of its 32 rows and 32 columns in LDS (16 bytes per lane, shared by the four
@@ -190,12 +273,18 @@ __device__ __forceinline__ void epilogue(const SplitArgs &g, int64_t mi, int64_t
 // or flushes its levels; this measured faster than a second buffer per workgroup.  Rows
 // and columns past the edge load the last valid one: they only reach outputs that are
 // never stored.
+//
+// LDS layout of a plane: row r's 64 bytes at 64 r, its four 16-byte quarters permuted by
+// f -> f ^ sw(r), sw(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1).  Four consecutive lanes still
+// fetch one row's 64 contiguous bytes from memory, and a fragment read (16 lanes, 16
+// consecutive rows, one quarter) then touches 16 distinct 16-byte bank groups, where the
+// unpermuted rows 64 bytes apart fell on the same banks every fourth row.
 template <int C, int S, int NO>
 __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   constexpr int W = 7;
   constexpr bool RE = NO == 1;
   constexpr int PL = S * 32 * 4;            // 16-byte pieces per operand per chunk
-  extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes]
+  extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes, permuted]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int64_t tm, tn;
   xcd_tile((g.m + 31) / 32, (g.n + 31) / 32, tm, tn);
@@ -204,6 +293,9 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   const int64_t bcol = n0 + (lane & 15);
   const int frow = 16 * (w >> 1) + (lane & 15), fcol = 16 * (w & 1) + (lane & 15);
   const int fk = lane >> 4;   // which 16-byte quarter of the 64-deep chunk
+  // LDS slots of this lane's quarter of its fragment row and column
+  const int xslot = frow * 4 + (fk ^ (((frow >> 1) & 3) ^ ((frow >> 3) & 1)));
+  const int yslot = fcol * 4 + (fk ^ (((fcol >> 1) & 3) ^ ((fcol >> 3) & 1)));
   const int8_t *xs = (const int8_t *)g.xs, *ys = (const int8_t *)g.ys;
   double lr[4][C], li[4][C];
 #pragma unroll
@@ -220,8 +312,15 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
     const int64_t mi = m0 + 4 * (lane >> 4) + e, nj = bcol;
     tsums[e] = (mi < g.m ? g.tx[mi] : 0) + (nj < g.n ? g.ty[nj] : 0);
   }
+  // the values of C this lane's outputs update, fetched now so that their latency
+  // overlaps the products
+  const int64_t rb = m0 + 4 * (lane >> 4);
+  const int nv = (bcol < g.n && rb < g.m) ? (int)(g.m - rb < 4 ? g.m - rb : 4) : 0;
+  double cv[RE ? C : 2 * C][4];
+  ld_col4<RE ? C : 2 * C>(g.Cm, g.ci + rb, g.cj + bcol, g.beta ? nv : 0, cv);
   const int nck = (int)(g.Kpad / 64);
-  // piece e = (plane p, row r, quarter f) of chunk `it` (product it / nck)
+  // piece e = (plane p, row r, LDS quarter slot f) of chunk `it` (product it / nck); the
+  // slot holds the row's quarter f ^ sw(r)
   auto issue = [&](int it) {
     const int op = it / nck;
     const int64_t kc = (int64_t)(it % nck) * 64;
@@ -230,7 +329,8 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
     v4i *dX = sdig, *dY = sdig + PL;
     for (int e0 = w * 64; e0 < PL; e0 += 256) {
       const int e = e0 + lane;
-      const int f = e & 3, r = (e >> 2) & 31, pl = e >> 7;
+      const int r = (e >> 2) & 31, pl = e >> 7;
+      const int f = (e & 3) ^ (((r >> 1) & 3) ^ ((r >> 3) & 1));
       const int64_t gi = (M0 + r < g.m) ? M0 + r : g.m - 1;
       const int64_t gj = (N0 + r < g.n) ? N0 + r : g.n - 1;
       __builtin_amdgcn_global_load_lds(
@@ -266,8 +366,8 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
       v4i a[S], b[S];
 #pragma unroll
       for (int p = 0; p < S; ++p) {
-        a[p] = sX[(p * 32 + frow) * 4 + fk];
-        b[p] = sY[(p * 32 + fcol) * 4 + fk];
+        a[p] = sX[p * 128 + xslot];
+        b[p] = sY[p * 128 + yslot];
       }
 #pragma unroll
       for (int p = 0; p < S; ++p)
@@ -301,8 +401,7 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
       }
     }
   }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) epilogue<C, RE>(g, m0 + 4 * (lane >> 4) + e, bcol, lr[e], li[e]);
+  epilogue4<C, RE>(g, rb, bcol, nv, lr, li, cv);
 }
 
 // FP64 digits, W = 22, K processed in blocks of 128 (the exactness limit of one level).

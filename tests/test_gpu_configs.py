@@ -14,6 +14,8 @@ size (the oracle's own LU would take minutes to hours here):
       residual of A^H g_b = c, the rank-16 update, and quadruple-double central
       differences (step 2^-60) on 32 entries
   metric  DD / QD n=4096: eta of the 3M factorisation
+  paper LU workload (Sec. 4) at n = 384-512: every update form against the oracle's
+      solution and against x_k = k + k i
 
 eta = ||b - A x||_inf / (||A||_inf ||x||_inf) always comes from an exact residual.
 """
@@ -338,3 +340,35 @@ def test_matmul_paper_workload_n2048_sampled(mp, orc, C):
     record("matmul_n2048", C=C, err_over_sum_abs=worst)
     del Ad, Bd
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("C,n", [(2, 512), (3, 384), (4, 384)])
+def test_paper_lu_workload_vs_oracle(mp, orc, C, n):
+    """The LU workload of Sec. 4 (leading components uniform on [0, 1], x_k = k + k i) at
+    a size the oracle factors in seconds, with b = A x formed exactly and rounded once to
+    the working format (the paper forms it at 2048 bits; exact-then-round is at least as
+    good).  Every trailing-update form, panel 64: the solution elementwise against the
+    oracle's solution and against x, each within 10 n kappa u (kappa from the oracle's
+    condition estimate), eta within 10 n u by the exact residual, and the maximum relative
+    error max_k |x_k - x*_k| / |x*_k| of the paper's tables recorded."""
+    A = orc.canon(synthgen.uniform(n, n, C, 5, lo=0.0, hi=1.0))
+    xt = synthgen.k_plus_ki(n, C)
+    b = orc.matmul_exact(A, xt)
+    xo, LUo, ipo, info_o = orc.gesv(A, b)
+    assert info_o == 0
+    kappa = orc.cond_inf_est(A, LUo, ipo)
+    xmod = np.sqrt(2.0) * np.arange(1, n + 1)
+    u = U_FMT[C]
+    out = {}
+    for method in ("4m", "3m", "split_i8", "split_f64"):
+        x, _, _, info, _ = gesv_gpu(mp, A, b, panel=64, method=method)
+        assert info == 0, method
+        fo, fx = fwd_err(x, xo, orc), fwd_err(x, xt, orc)
+        rel = float((np.abs(orc.diff(np.ascontiguousarray(x), xt))[:, 0] / xmod).max())
+        eta = orc.backward_error(A, x, b)
+        out[method] = dict(eta=eta, fwd_vs_oracle=fo, fwd=fx, max_rel_err=rel)
+        assert fo <= 10 * n * kappa * u, method
+        assert fx <= 10 * n * kappa * u, method
+        assert eta <= 10 * n * u, method
+    fo_oracle = fwd_err(xo, xt, orc)
+    record("paper_lu", C=C, n=n, kappa=kappa, oracle_fwd=fo_oracle, **out)
