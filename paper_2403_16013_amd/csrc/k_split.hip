@@ -354,34 +354,31 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   // above that level would only pass it down unchanged.  (For DD the saving is one
   // TwoSum per group, and the shorter code needed more VGPRs than two waves per SIMD
   // allow.)
-  v4i acc[S];
+  // The levels of a finished product are copied out of the accumulators and pushed into
+  // the multi-component sums while the next product's first chunk is in flight.
+  v4i acc[S], snap[S];
 #pragma unroll
   for (int l = 0; l < S; ++l) acc[l] = v4i{0, 0, 0, 0};
-  for (int op = 0; op < NO; ++op) {
-    for (int c = 0; c < nck; ++c) {
-      issue(op * nck + c);
-      __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces of the chunk have landed
-      __syncthreads();                // and everybody else's
-      const v4i *sX = sdig, *sY = sdig + PL;
-      v4i a[S], b[S];
+  auto chunk = [&]() {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces of the chunk have landed
+    __syncthreads();                // and everybody else's
+    const v4i *sX = sdig, *sY = sdig + PL;
+    v4i a[S], b[S];
 #pragma unroll
-      for (int p = 0; p < S; ++p) {
-        a[p] = sX[p * 128 + xslot];
-        b[p] = sY[p * 128 + yslot];
-      }
-#pragma unroll
-      for (int p = 0; p < S; ++p)
-#pragma unroll
-        for (int q = 0; q < S - p; ++q)
-          acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
-      __syncthreads();  // the buffer is refilled next
+    for (int p = 0; p < S; ++p) {
+      a[p] = sX[p * 128 + xslot];
+      b[p] = sY[p * 128 + yslot];
     }
-    if (!RE && op == 1) {
 #pragma unroll
-      for (int l = 0; l < S; ++l) acc[l] = -acc[l];  // -T1 - T2
-    }
-    // where the levels go: op 0 twice to the real part (a real product: once), op 1 to
-    // the real part, op 2 to the imaginary part
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int q = 0; q < S - p; ++q)
+        acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
+    __syncthreads();  // the buffer is refilled next
+  };
+  // where the levels of product op go: op 0 twice to the real part (a real product:
+  // once), op 1 to the real part, op 2 to the imaginary part
+  auto flush = [&](int op) {
     const int sc = (!RE && op == 0) ? 1 : 0;  // power of two
     const bool to_re = RE || op < 2;
 #pragma unroll
@@ -394,13 +391,29 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
         double grp = 0.0;
 #pragma unroll
         for (int l = top; l >= lo; --l)
-          grp = __builtin_fma((double)acc[l][e], ldexp(1.0, (lo - l) * W), grp);
+          grp = __builtin_fma((double)snap[l][e], ldexp(1.0, (lo - l) * W), grp);
         grp = ldexp(grp, tsum - (lo + 2) * W);
         if (to_re) mp::push<C>(lr[e], lvl, grp);
         else mp::push<C>(li[e], lvl, grp);
       }
     }
+  };
+  for (int op = 0; op < NO; ++op) {
+    issue(op * nck);
+    if (op > 0) flush(op - 1);
+    chunk();
+    for (int c = 1; c < nck; ++c) {
+      issue(op * nck + c);
+      chunk();
+    }
+    if (!RE && op == 1) {
+#pragma unroll
+      for (int l = 0; l < S; ++l) acc[l] = -acc[l];  // -T1 - T2
+    }
+#pragma unroll
+    for (int l = 0; l < S; ++l) snap[l] = acc[l];
   }
+  flush(NO - 1);
   epilogue4<C, RE>(g, rb, bcol, nv, lr, li, cv);
 }
 
