@@ -32,6 +32,7 @@ struct SliceArgs {
   int64_t i0, j0;
   int trans;  // element (v, t) = trans ? M(i0 + t, j0 + v) : M(i0 + v, j0 + t)
   int conj;   // negate the imaginary part
+  int neg3;   // negate the digits of the third operand set (Re + Im)
   int64_t nvec, K, Kpad;
   void *out;      // [3][S][nvec][Kpad] digits (int8 or double)
   int32_t *tau;   // [3][nvec]
@@ -124,7 +125,9 @@ __global__ __launch_bounds__(256) void k_slice(SliceArgs a) {
           r[c - 1] = s;
           r[c] = e;
         }
-        out[(((int64_t)o * S + (p - 1)) * a.nvec + v) * a.Kpad + t] = (T)d;
+        // RN digits of -x are those of x negated
+        out[(((int64_t)o * S + (p - 1)) * a.nvec + v) * a.Kpad + t] =
+            (T)((o == 2 && a.neg3) ? -d : d);
       }
     }
   }
@@ -319,41 +322,55 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   double cv[RE ? C : 2 * C][4];
   ld_col4<RE ? C : 2 * C>(g.Cm, g.ci + rb, g.cj + bcol, g.beta ? nv : 0, cv);
   const int nck = (int)(g.Kpad / 64);
-  // piece e = (plane p, row r, LDS quarter slot f) of chunk `it` (product it / nck); the
-  // slot holds the row's quarter f ^ sw(r)
+  // The fill: piece e = (plane p, row r, LDS quarter slot f) of a chunk goes to slot e of
+  // the staging buffer and holds the row's quarter f ^ sw(r).  Wave w fills the pieces
+  // w * 64 + 256 i + lane: planes 2 i + w / 2, rows 16 (w & 1) + lane / 4, slot lane & 3,
+  // so each lane's source row and quarter are the same in every plane and chunk.
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const int8_t *px, *py;
+  {
+    const int r = 16 * (wu & 1) + (lane >> 2);
+    const int f = (lane & 3) ^ (((r >> 1) & 3) ^ ((r >> 3) & 1));
+    const int64_t gi = (M0 + r < g.m) ? M0 + r : g.m - 1;
+    const int64_t gj = (N0 + r < g.n) ? N0 + r : g.n - 1;
+    px = xs + gi * g.Kpad + 16 * f;
+    py = ys + gj * g.Kpad + 16 * f;
+  }
+  const int64_t psx = g.m * g.Kpad, psy = g.n * g.Kpad;  // plane strides
+  // chunk `it` (product it / nck)
   auto issue = [&](int it) {
     const int op = it / nck;
-    const int64_t kc = (int64_t)(it % nck) * 64;
-    const int8_t *xo = xs + (int64_t)op * S * g.m * g.Kpad;
-    const int8_t *yo = ys + (int64_t)op * S * g.n * g.Kpad;
+    const int64_t kc = (int64_t)(it - op * nck) * 64;
+    const int pl0 = op * S + (wu >> 1);
+    const int8_t *qx = px + pl0 * psx + kc, *qy = py + pl0 * psy + kc;
     v4i *dX = sdig, *dY = sdig + PL;
-    for (int e0 = w * 64; e0 < PL; e0 += 256) {
-      const int e = e0 + lane;
-      const int r = (e >> 2) & 31, pl = e >> 7;
-      const int f = (e & 3) ^ (((r >> 1) & 3) ^ ((r >> 3) & 1));
-      const int64_t gi = (M0 + r < g.m) ? M0 + r : g.m - 1;
-      const int64_t gj = (N0 + r < g.n) ? N0 + r : g.n - 1;
-      __builtin_amdgcn_global_load_lds(
-          (const void *)(xo + ((int64_t)pl * g.m + gi) * g.Kpad + kc + 16 * f),
-          (__attribute__((address_space(3))) void *)(dX + e0), 16, 0, 0);
-      __builtin_amdgcn_global_load_lds(
-          (const void *)(yo + ((int64_t)pl * g.n + gj) * g.Kpad + kc + 16 * f),
-          (__attribute__((address_space(3))) void *)(dY + e0), 16, 0, 0);
+#pragma unroll
+    for (int i = 0; i < (S + 1) / 2; ++i) {
+      if (2 * i + (wu >> 1) < S) {
+        const int e0 = wu * 64 + 256 * i;
+        __builtin_amdgcn_global_load_lds((const void *)qx,
+                                         (__attribute__((address_space(3))) void *)(dX + e0),
+                                         16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)qy,
+                                         (__attribute__((address_space(3))) void *)(dY + e0),
+                                         16, 0, 0);
+      }
+      qx += 2 * psx;
+      qy += 2 * psy;
     }
   };
   // Level l (0-based) of a product carries weight 2^(tau_i + tau_j - (l + 2) W), the same
   // for the three products of Eq. 3m_cemm (one exponent per row / column for all three),
-  // so they combine exactly in INT32 in one set of level accumulators: after T1, twice
-  // T1 goes to the real part; T2 is added and the sum negated, -T1 - T2 goes to the real
-  // part too (which now holds T1 - T2) and is where the accumulation of T3 starts, which
-  // leaves I = T3 - T1 - T2 for the imaginary part.  Three flushes instead of five.
+  // so they combine exactly in INT32 in one set of level accumulators.  The digits of the
+  // third operand set of op(A) arrive negated, so the accumulators hold T1, then T1 + T2,
+  // then T1 + T2 - T3: twice the first goes to the real part, the second is subtracted
+  // from it (leaving T1 - T2) and the third is subtracted from the imaginary part
+  // (leaving T3 - T1 - T2).  Three flushes instead of five.
   // Four consecutive levels span at most 26 + 3 W bits (|sum| < 3 x 64 S 65^2 per chunk,
   // below 2^31 by the depth limit), so their scaled sum is exact in binary64.  A group
-  // starting at level lo is at most 2^(-lo W) of the largest possible level-0 sum, so for
-  // TD and QD it enters the accumulator at component level lo W / 53: the TwoSum steps
-  // above that level would only pass it down unchanged.  (For DD the saving is one
-  // TwoSum per group, and the shorter code needed more VGPRs than two waves per SIMD
-  // allow.)
+  // starting at level lo is at most 2^(-lo W) of the largest possible level-0 sum, so it
+  // enters the accumulator at component level lo W / 53: the TwoSum steps above that
+  // level would only pass it down unchanged.
   // The levels of a finished product are copied out of the accumulators and pushed into
   // the multi-component sums while the next product's first chunk is in flight.
   v4i acc[S], snap[S];
@@ -376,23 +393,25 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
         acc[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[p], b[q], acc[p + q], 0, 0, 0);
     __syncthreads();  // the buffer is refilled next
   };
-  // where the levels of product op go: op 0 twice to the real part (a real product:
-  // once), op 1 to the real part, op 2 to the imaginary part
+  // product op: its levels scaled by 2 and added (op 0), or subtracted (ops 1 and 2); op 2
+  // goes to the imaginary part.  A real product (one operand set) adds its levels to the
+  // real part.
   auto flush = [&](int op) {
     const int sc = (!RE && op == 0) ? 1 : 0;  // power of two
     const bool to_re = RE || op < 2;
+    const bool sub = !RE && op > 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int tsum = tsums[e] + sc;
 #pragma unroll
       for (int top = S - 1; top >= 0; top -= 4) {
         const int lo = top - 3 < 0 ? 0 : top - 3;
-        const int lvl = C == 2 ? 0 : ((lo * W) / 53 < C - 1 ? (lo * W) / 53 : C - 1);
+        const int lvl = (lo * W) / 53 < C - 1 ? (lo * W) / 53 : C - 1;
         double grp = 0.0;
 #pragma unroll
         for (int l = top; l >= lo; --l)
           grp = __builtin_fma((double)snap[l][e], ldexp(1.0, (lo - l) * W), grp);
-        grp = ldexp(grp, tsum - (lo + 2) * W);
+        grp = ldexp(sub ? -grp : grp, tsum - (lo + 2) * W);
         if (to_re) mp::push<C>(lr[e], lvl, grp);
         else mp::push<C>(li[e], lvl, grp);
       }
@@ -406,12 +425,13 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
       issue(op * nck + c);
       chunk();
     }
-    if (!RE && op == 1) {
+    // the copy lives in VGPRs; without the opaque step the compiler would keep reading
+    // the old accumulators and give the next product a second set (twice the registers)
 #pragma unroll
-      for (int l = 0; l < S; ++l) acc[l] = -acc[l];  // -T1 - T2
+    for (int l = 0; l < S; ++l) {
+      snap[l] = acc[l];
+      asm volatile("" : "+v"(snap[l]));
     }
-#pragma unroll
-    for (int l = 0; l < S; ++l) snap[l] = acc[l];
   }
   flush(NO - 1);
   epilogue4<C, RE>(g, rb, bcol, nv, lr, li, cv);
@@ -521,10 +541,12 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
   char *p = (char *)ws;
   SliceArgs sx, sy;
   sx.M = A; sx.i0 = ai; sx.j0 = aj; sx.trans = (opA != 'N'); sx.conj = (opA == 'C');
+  sx.neg3 = I8 && NO == 3;  // k_split_i8 forms -T3 (see there)
   sx.nvec = m; sx.K = k; sx.Kpad = Kp;
   sx.out = p;
   p += al256(sizeof(T) * 3 * (size_t)S * (size_t)m * (size_t)Kp);
   sy.M = B; sy.i0 = bi; sy.j0 = bj; sy.trans = (opB == 'N'); sy.conj = (opB == 'C');
+  sy.neg3 = 0;
   sy.nvec = n; sy.K = k; sy.Kpad = Kp;
   sy.out = p;
   p += al256(sizeof(T) * 3 * (size_t)S * (size_t)n * (size_t)Kp);
