@@ -489,6 +489,9 @@ def main():
     if not args.no_roofline:
         line["roofline_split_i8"] = split_roofline(mp, torch, A0, 128)
         print(f"[bench] split roofline {line['roofline_split_i8']}", file=sys.stderr, flush=True)
+        line["roofline_split_i8_k64"] = split_roofline(mp, torch, A0, 64)
+        print(f"[bench] split roofline K=64 {line['roofline_split_i8_k64']}", file=sys.stderr,
+              flush=True)
     if not args.no_variants:
         var = {}
         # the metric's grid: DD / TD / QD x {4M, 3M, split INT8, split FP64}, panels 64

@@ -94,14 +94,16 @@ PanelGeom panel_geometry(int C, int64_t mp, int kb) {
   // largest row count per workgroup that fits in LDS (and one row per thread)
   int rmax = PNT;
   while (rmax > 1 && panel_lds(C, kb, rmax) > PLDS_BUDGET) --rmax;
-  // aim for about 96 workgroups: fewer makes the per-column barrier cheaper, more
-  // spreads the rank-1 work; never below 8 rows each
+  // aim for about 64 workgroups for double-double and 96 for the wider formats: fewer
+  // makes the per-column barrier cheaper, more spreads the rank-1 work, whose share grows
+  // with the format (measured at n = 4096, panel 64); never below 8 rows each
   // (MPLU_PANEL_WGS and MPLU_PANEL_RMIN override the target and the row floor, for tuning)
-  static const int target = [] {
+  static const int forced = [] {
     const char *e = getenv("MPLU_PANEL_WGS");
-    const int t = e ? atoi(e) : 96;
-    return t < 1 ? 96 : t;
+    const int t = e ? atoi(e) : 0;
+    return t < 1 ? 0 : t;
   }();
+  const int target = forced ? forced : (C == 2 ? 64 : 96);
   static const int rmin = [] {
     const char *e = getenv("MPLU_PANEL_RMIN");
     const int t = e ? atoi(e) : 8;

@@ -275,19 +275,15 @@ __device__ __forceinline__ void epilogue4(const SplitArgs &g, int64_t i, int64_t
 // share a CU (for double-double), so one's MFMAs run while the other waits for its planes
 // or flushes its levels; this measured faster than a second buffer per workgroup.  Rows
 // and columns past the edge load the last valid one: they only reach outputs that are
-// never stored.
-//
-// LDS layout of a plane: row r's 64 bytes at 64 r, its four 16-byte quarters permuted by
-// f -> f ^ sw(r), sw(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1).  Four consecutive lanes still
-// fetch one row's 64 contiguous bytes from memory, and a fragment read (16 lanes, 16
-// consecutive rows, one quarter) then touches 16 distinct 16-byte bank groups, where the
-// unpermuted rows 64 bytes apart fell on the same banks every fourth row.
+// never stored.  (A permutation of each row's four 16-byte quarters in LDS, spreading a
+// fragment read's 16 rows over distinct banks, measured no faster and left the
+// bank-conflict counter unchanged.)
 template <int C, int S, int NO>
 __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   constexpr int W = 7;
   constexpr bool RE = NO == 1;
   constexpr int PL = S * 32 * 4;            // 16-byte pieces per operand per chunk
-  extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes, permuted]
+  extern __shared__ v4i sdig[];             // [2][S][32 rows][4 x 16 bytes]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int64_t tm, tn;
   xcd_tile((g.m + 31) / 32, (g.n + 31) / 32, tm, tn);
@@ -297,8 +293,7 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   const int frow = 16 * (w >> 1) + (lane & 15), fcol = 16 * (w & 1) + (lane & 15);
   const int fk = lane >> 4;   // which 16-byte quarter of the 64-deep chunk
   // LDS slots of this lane's quarter of its fragment row and column
-  const int xslot = frow * 4 + (fk ^ (((frow >> 1) & 3) ^ ((frow >> 3) & 1)));
-  const int yslot = fcol * 4 + (fk ^ (((fcol >> 1) & 3) ^ ((fcol >> 3) & 1)));
+  const int xslot = frow * 4 + fk, yslot = fcol * 4 + fk;
   const int8_t *xs = (const int8_t *)g.xs, *ys = (const int8_t *)g.ys;
   double lr[4][C], li[4][C];
 #pragma unroll
@@ -322,15 +317,15 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
   double cv[RE ? C : 2 * C][4];
   ld_col4<RE ? C : 2 * C>(g.Cm, g.ci + rb, g.cj + bcol, g.beta ? nv : 0, cv);
   const int nck = (int)(g.Kpad / 64);
-  // The fill: piece e = (plane p, row r, LDS quarter slot f) of a chunk goes to slot e of
-  // the staging buffer and holds the row's quarter f ^ sw(r).  Wave w fills the pieces
-  // w * 64 + 256 i + lane: planes 2 i + w / 2, rows 16 (w & 1) + lane / 4, slot lane & 3,
-  // so each lane's source row and quarter are the same in every plane and chunk.
+  // The fill: piece e = (plane p, row r, quarter f) of a chunk goes to slot e of the
+  // staging buffer.  Wave w fills the pieces w * 64 + 256 i + lane: planes 2 i + w / 2,
+  // rows 16 (w & 1) + lane / 4, quarter lane & 3, so each lane's source row and quarter
+  // are the same in every plane and chunk.
   const int wu = __builtin_amdgcn_readfirstlane(w);
   const int8_t *px, *py;
   {
     const int r = 16 * (wu & 1) + (lane >> 2);
-    const int f = (lane & 3) ^ (((r >> 1) & 3) ^ ((r >> 3) & 1));
+    const int f = lane & 3;
     const int64_t gi = (M0 + r < g.m) ? M0 + r : g.m - 1;
     const int64_t gj = (N0 + r < g.n) ? N0 + r : g.n - 1;
     px = xs + gi * g.Kpad + 16 * f;
