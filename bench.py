@@ -495,13 +495,15 @@ def main():
     if not args.no_variants:
         var = {}
         # the metric's grid: DD / TD / QD x {4M, 3M, split INT8, split FP64}, panels 64
-        # and 128 (DD 3M at the headline's panel is the headline itself)
+        # and 128 (DD 3M at the headline's panel is the headline itself), and the
+        # Strassen-Winograd LU of Table 1
         runs = ((2, "4m", panel, 2), (2, "3m", 128, 2), (2, "split_i8", panel, 2),
-                (2, "split_i8", 128, 2), (2, "split_f64", panel, 1), (2, "split_f64", 128, 1))
+                (2, "split_i8", 128, 2), (2, "split_f64", panel, 1), (2, "split_f64", 128, 1),
+                (2, "strassen", panel, 1))
         for C in (3, 4):
             runs += ((C, "3m", panel, 1), (C, "3m", 128, 1), (C, "4m", panel, 1),
                      (C, "split_i8", panel, 1), (C, "split_i8", 128, 1),
-                     (C, "split_f64", panel, 1))
+                     (C, "split_f64", panel, 1), (C, "strassen", panel, 1))
         probs = {2: (A0, B0)}
         for (C, meth, pnl, steps) in runs:
             if C not in probs:

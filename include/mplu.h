@@ -52,8 +52,10 @@ typedef enum {
   MPLU_GEMM_3M = 1,        /* Eq. 3m_cemm: three real products plus additions           */
   MPLU_GEMM_SPLIT_F64 = 2, /* Sec. 2.3 Ozaki scheme: exact slice products on FP64 MFMA  */
   MPLU_GEMM_SPLIT_I8 = 3,  /* same split with 7-bit INT8 slices, exact INT32 sums       */
-  MPLU_GEMM_STRASSEN = 4   /* mplu_zgemm only ('N', 'N'): one level of Winograd's variant
-                              of Strassen's algorithm over 3M products (Sec. 2.1)        */
+  MPLU_GEMM_STRASSEN = 4   /* one level of Winograd's variant of Strassen's algorithm
+                              over 3M products (Sec. 2.1): mplu_zgemm ('N', 'N') and the
+                              trailing updates of the complex mplu_zgetrf / mplu_zgesv
+                              (the Strassen LU of Sec. 3 / Table 1)                      */
 } mplu_gemm_t;
 
 /* A complex multi-component matrix: see NUMBER FORMAT above. */
@@ -69,7 +71,9 @@ typedef struct {
                          held in LDS); >= min(m, n) gives the unblocked LU, which therefore
                          needs min(m, n) <= 128; an effective width min(panel, min(m, n))
                          above 128 makes mplu_zgetrf return MPLU_E_UNSUPPORTED          */
-  int32_t gemm;       /* mplu_gemm_t for the trailing update [MPLU_GEMM_3M]                 */
+  int32_t gemm;       /* mplu_gemm_t for the trailing update [MPLU_GEMM_3M]; with
+                         MPLU_GEMM_STRASSEN the look-ahead's narrow product of the next
+                         panel's columns stays plain 3M                                   */
   int32_t n_slices;   /* split methods: slices per operand, 0 = automatic                   */
   int32_t slice_bits; /* split methods: bits per slice, 0 = automatic                       */
   int32_t flags;      /* MPLU_FLAG_* bits [0]                                               */
@@ -223,7 +227,8 @@ int mplu_zgemm(int prec, char opA, char opB, int64_t m, int64_t n, int64_t k,
  * reciprocal), interchanges, triangular solves and substitutions, and the real product
  * (only T1 = Re(L21) Re(U12) of Eq. 3m_cemm) for the trailing and block updates.
  * opts->gemm: MPLU_GEMM_4M and MPLU_GEMM_3M both select the real product; the split
- * methods split the real operands (one real product of digit pairs instead of three).
+ * methods split the real operands (one real product of digit pairs instead of three);
+ * MPLU_GEMM_STRASSEN is complex only (MPLU_E_UNSUPPORTED).
  * Argument meaning, pivots, d_info, ownership, errors and workspace sizes are as for the
  * complex routines.
  */

@@ -68,6 +68,11 @@ inline bool is_split(int method) {
   return method == MPLU_GEMM_SPLIT_F64 || method == MPLU_GEMM_SPLIT_I8;
 }
 
+// one Winograd level over 3M products (defined below with its workspace layout)
+size_t strassen_ws(int C, int64_t m, int64_t n, int64_t k);
+hipError_t strassen_zgemm(int C, int64_t m, int64_t n, int64_t k, int alpha, ZM A, ZM B,
+                          int beta, ZM Cm, void *ws, hipStream_t s);
+
 // slice options: n_slices 0 = default; slice_bits 0 or the fixed digit width (7 for INT8,
 // 22 for FP64)
 inline bool split_opts_ok(int C, int method, const mplu_opts_t *o) {
@@ -100,6 +105,9 @@ GetrfWS getrf_layout(int C, int64_t m, int64_t n, const mplu_opts_t *o) {
     const int S = o ? o->n_slices : 0;
     w.split_rest = align256(split_ws_bytes(C, i8, m, n, kb, S));
     w.split_next = align256(split_ws_bytes(C, i8, m, kb, kb, S));
+  } else if (method == MPLU_GEMM_STRASSEN) {
+    // the rest of the trailing matrix (the next panel's columns use plain 3M)
+    w.split_rest = align256(strassen_ws(C, m, n, kb));
   }
   w.total = 3 * w.panel + w.split_rest + w.split_next;
   return w;
@@ -141,6 +149,10 @@ hipError_t step_trsm(int C, ZM a, int64_t j, int jb, int64_t c0, int64_t c1, hip
 hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
                      int64_t c1, void *split_ws, hipStream_t s, bool real) {
   if (c1 <= c0 || j + jb >= m) return hipSuccess;
+  if (method == MPLU_GEMM_STRASSEN)  // complex only (getrf_core rejects it for real)
+    return strassen_zgemm(C, m - j - jb, c1 - c0, jb, -1, ZM{a.p + j * a.ld + j + jb, a.ld, a.ps},
+                          ZM{a.p + c0 * a.ld + j, a.ld, a.ps},
+                          1, ZM{a.p + c0 * a.ld + j + jb, a.ld, a.ps}, split_ws, s);
   if (is_split(method))
     return launch_gemm_split(C, method == MPLU_GEMM_SPLIT_I8, S, 'N', 'N', m - j - jb, c1 - c0,
                              jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, split_ws, s,
@@ -308,8 +320,9 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     return -7;
   const int method = gemm_method(opts);
   if (method != MPLU_GEMM_4M && method != MPLU_GEMM_3M && method != MPLU_GEMM_SPLIT_F64 &&
-      method != MPLU_GEMM_SPLIT_I8)
+      method != MPLU_GEMM_SPLIT_I8 && method != MPLU_GEMM_STRASSEN)
     return -7;
+  if (real && method == MPLU_GEMM_STRASSEN) return MPLU_E_UNSUPPORTED;
   if (!split_opts_ok(prec, method, opts)) return MPLU_E_UNSUPPORTED;
   {
     // the panel is held in LDS: widths up to kMaxPanel (a width >= min(m, n) asks for the
@@ -379,8 +392,11 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
     HIPCHK(hipStreamWaitEvent(b, ev.panel, 0));
     if (nx1 > nx0) {
       // the next panel's columns: interchanges and U12 in one launch, then the product
+      // (with Strassen chosen, this narrow product on the critical path stays plain 3M:
+      // the fifteen block sums would only add launches to it)
       HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb), real));
-      HIPCHK(step_gemm(C, method, S, a, m, j, jb, nx0, nx1, split_next, s, real));
+      HIPCHK(step_gemm(C, method == MPLU_GEMM_STRASSEN ? MPLU_GEMM_3M : method, S, a, m, j, jb,
+                       nx0, nx1, split_next, s, real));
     }
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device

@@ -106,12 +106,20 @@ def test_argument_checks(L):
     assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 2, d, d, 0, d, None) == -7
     assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 1, d, d, 2, d, None) == -10
     assert L.mplu_dgemm(2, b"N", b"N", 4, 4, 4, 1, d, d, 0, dnull, None) == -11
-    # Strassen-Winograd: 'N', 'N' products only, not a trailing-update choice
+    # Strassen-Winograd: 'N', 'N' products; a trailing-update choice of the complex LU
+    # only (its workspace holds the update's product and two half-size operand sums)
     assert L.mplu_zgemm(2, b"T", b"N", 4, 4, 4, 1, z, z, 0, z, 4, None, wk, 1 << 30, None) == -102
     assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 0, z, 4, None, wk, 16, None) == -100
     assert L.mplu_zgemm(2, b"N", b"N", 4, 4, 4, 1, z, z, 0, z, 5, None, wk, 0, None) == -12
     st = m.Opts(64, 4, 0, 0, 0)
-    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(st), wk, 1 << 30, None) == -7
+    assert L.mplu_dgetrf(2, 8, 8, d, ip, inf, ct.byref(st), wk, 1 << 30, None) == -102
+    assert L.mplu_dgesv(2, 8, 1, d, ip, d, inf, ct.byref(st), wk, 1 << 30, None) == -102
+    assert L.mplu_zgetrf(2, 8, 8, z, ip, inf, ct.byref(st), wk, 16, None) == -100
+    three = m.Opts(64, 1, 0, 0, 0)
+    ws3, wss = ct.c_size_t(), ct.c_size_t()
+    assert L.mplu_zgetrf_wsbytes(2, 4096, 4096, ct.byref(three), ct.byref(ws3)) == 0
+    assert L.mplu_zgetrf_wsbytes(2, 4096, 4096, ct.byref(st), ct.byref(wss)) == 0
+    assert wss.value - ws3.value >= 2 * 2 * 8 * 4096 * 4096  # the m x n product W
     # panel widths above 128 (the LDS-resident panel) are refused, not clamped; a width
     # >= min(m, n) asks for the unblocked LU, possible only for min(m, n) <= 128
     big = m.ZMat(0x1000, 4096, 4096 * 4096)

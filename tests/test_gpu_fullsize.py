@@ -51,14 +51,14 @@ def system_n4096(orc, C):
 
 GRID = [(C, meth, K) for C in (2, 3, 4)
         for meth, K in (("3m", 64), ("3m", 128), ("4m", 64), ("split_i8", 64),
-                        ("split_i8", 128), ("split_f64", 64))]
+                        ("split_i8", 128), ("split_f64", 64), ("strassen", 64))]
 
 
 @pytest.mark.parametrize("C,method,panel", GRID)
 def test_eta_n4096_every_form(mp, orc, C, method, panel):
     """eta = ||b - A x|| / (||A|| ||x||) <= 10 n u by the oracle's exact residual, for
-    DD / TD / QD and the 3M, 4M and both split trailing updates (Sec. 3, Table 1's
-    comparison of LU forms)."""
+    DD / TD / QD and the 3M, 4M, both split and the Strassen-Winograd trailing updates
+    (Sec. 3, Table 1's comparison of LU forms)."""
     import torch
 
     n = 4096

@@ -136,6 +136,26 @@ def test_getrf_blocked_vs_oracle(mp, orc, C, method):
     _lu_parity(mp, orc, C, 200, 64, method, 30 + C)
 
 
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("n", [200, 203])
+def test_getrf_strassen_vs_oracle(mp, orc, C, n):
+    """The Strassen LU (Sec. 3, Table 1): trailing updates by one Winograd level over 3M
+    (odd sizes peeled), the look-ahead's next-panel product in 3M; pivots and factors
+    against the oracle, with and without the look-ahead."""
+    _lu_parity(mp, orc, C, n, 64, "strassen", 50 + C)
+    A = orc.canon(synthgen.uniform(n, n, C, 50 + C))
+    LUo, ipo, _ = orc.getf2(A)
+    T = to_dev(A)
+    ipiv, info = mp.getrf(T, panel=64, method="strassen", lookahead=False)
+    sync()
+    assert int(info.item()) == 0
+    k_clear = pivot_gaps_clear(orc.hi_complex(LUo))
+    assert np.array_equal(ipiv.cpu().numpy()[:k_clear], ipo[:k_clear])
+    if k_clear == n:
+        d = orc.diff(to_host(T), LUo)
+        assert np.abs(d).max() <= 100 * n * U_FMT[C] * np.abs(orc.hi_complex(LUo)).max()
+
+
 @pytest.mark.parametrize("C", [2])
 def test_getrf_unblocked_c1(mp, orc, C):
     """n = 64, panel = n (the unblocked "Normal LU"), 4M."""
