@@ -456,25 +456,42 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
       const int lo = (int)(k - r0 > 0 ? k - r0 : 0);  // rows with local index >= k
       const int cnt = nr - lo;
       const int ncol = kb - k - 1;
+      const int tot = cnt * ncol;
       const int pt = (w == 0) ? t : t - 64;  // thread index among waves 0, 2 and 3
-      for (int e = pt; e < cnt * ncol; e += PNT - 64) {
-        const int r = lo + e % cnt;
-        const int c = k + 1 + e / cnt;
-        double xr[C], xi[C], lr_[C], li[C], ur[C], ui[C];
+      // two elements per pass, both loaded before either is computed: their dependent
+      // chains of FP64 operations interleave (a lone wave per SIMD otherwise waits out
+      // each operation's latency; the wider formats spend most of a column here)
+      for (int e = pt; e < tot; e += 2 * (PNT - 64)) {
+        const bool two = e + (PNT - 64) < tot;
+        const int ee[2] = {e, two ? e + (PNT - 64) : e};
+        double xr[2][C], xi[2][C], lr_[2][C], li[2][C], ur[2][C], ui[2][C];
 #pragma unroll
-        for (int cc = 0; cc < C; ++cc) {
-          xr[cc] = SA(c, cc, r);
-          xi[cc] = RE ? 0.0 : SA(c, C + cc, r);
-          lr_[cc] = SA(k - 1, cc, r);
-          li[cc] = RE ? 0.0 : SA(k - 1, C + cc, r);
-          ur[cc] = sPrev[cc * kb + c];
-          ui[cc] = RE ? 0.0 : sPrev[(C + cc) * kb + c];
+        for (int h = 0; h < 2; ++h) {
+          const int r = lo + ee[h] % cnt;
+          const int c = k + 1 + ee[h] / cnt;
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc) {
+            xr[h][cc] = SA(c, cc, r);
+            xi[h][cc] = RE ? 0.0 : SA(c, C + cc, r);
+            lr_[h][cc] = SA(k - 1, cc, r);
+            li[h][cc] = RE ? 0.0 : SA(k - 1, C + cc, r);
+            ur[h][cc] = sPrev[cc * kb + c];
+            ui[h][cc] = RE ? 0.0 : sPrev[(C + cc) * kb + c];
+          }
         }
-        pv_fms<C, RE>(xr, xi, lr_, li, ur, ui, xr, xi);
 #pragma unroll
-        for (int cc = 0; cc < C; ++cc) {
-          SA(c, cc, r) = xr[cc];
-          if (!RE) SA(c, C + cc, r) = xi[cc];
+        for (int h = 0; h < 2; ++h)
+          pv_fms<C, RE>(xr[h], xi[h], lr_[h], li[h], ur[h], ui[h], xr[h], xi[h]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h == 1 && !two) break;
+          const int r = lo + ee[h] % cnt;
+          const int c = k + 1 + ee[h] / cnt;
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc) {
+            SA(c, cc, r) = xr[h][cc];
+            if (!RE) SA(c, C + cc, r) = xi[h][cc];
+          }
         }
       }
     }
