@@ -138,16 +138,18 @@ struct LookaheadEvents {
 
 // the trailing update of one step restricted to columns [c0, c1): U12 := L11^-1 A12 on
 // those columns, then A22 -= L21 U12 on them
+// urgent: the next panel's columns, on the critical path of the look-ahead schedule
 hipError_t step_trsm(int C, ZM a, int64_t j, int jb, int64_t c0, int64_t c1, hipStream_t s,
-                     const int32_t *swl, bool real) {
+                     const int32_t *swl, bool real, bool urgent = false) {
   if (c1 <= c0) return hipSuccess;
-  return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s, swl, 2 * jb, real);
+  return launch_trsm(C, true, true, false, a, j, jb, a, j, c0, c1 - c0, s, swl, 2 * jb, real,
+                     urgent);
 }
 
 // real: a real matrix (the split methods then split real operands; the others use the
 // real product)
 hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
-                     int64_t c1, void *split_ws, hipStream_t s, bool real) {
+                     int64_t c1, void *split_ws, hipStream_t s, bool real, bool urgent = false) {
   if (c1 <= c0 || j + jb >= m) return hipSuccess;
   if (method == MPLU_GEMM_STRASSEN)  // complex only (getrf_core rejects it for real)
     return strassen_zgemm(C, m - j - jb, c1 - c0, jb, -1, ZM{a.p + j * a.ld + j + jb, a.ld, a.ps},
@@ -159,7 +161,8 @@ hipError_t step_gemm(int C, int method, int S, ZM a, int64_t m, int64_t j, int j
                              real);
   if (real) method = kGemmReal;
   return launch_gemm(C, method == kGemmReal ? 2 : (method == MPLU_GEMM_3M ? 1 : 0), 'N', 'N',
-                     m - j - jb, c1 - c0, jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, s);
+                     m - j - jb, c1 - c0, jb, -1, a, j + jb, j, a, j, c0, 1, a, j + jb, c0, s,
+                     urgent);
 }
 
 hipError_t step_update(int C, int method, int S, ZM a, int64_t m, int64_t j, int jb, int64_t c0,
@@ -394,9 +397,9 @@ int getrf_core(int prec, int64_t m, int64_t n, mplu_zmat_t A, int32_t *d_ipiv,
       // the next panel's columns: interchanges and U12 in one launch, then the product
       // (with Strassen chosen, this narrow product on the critical path stays plain 3M:
       // the fifteen block sums would only add launches to it)
-      HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb), real));
+      HIPCHK(step_trsm(C, a, j, jb, nx0, nx1, s, panel_swap_list(pw, C, jb), real, true));
       HIPCHK(step_gemm(C, method == MPLU_GEMM_STRASSEN ? MPLU_GEMM_3M : method, S, a, m, j, jb,
-                       nx0, nx1, split_next, s, real));
+                       nx0, nx1, split_next, s, real, true));
     }
     // the second stream's product waits until the next panel is about to start, so the
     // panel's workgroups are dispatched before the product fills the device

@@ -138,15 +138,20 @@ hipError_t launch_laswp_list(int C, ZM A, int64_t c0, int64_t ncols, const int32
 // swl (optional): interchange list (as left by a panel of width swstride / 2) applied to
 // those columns of Xm first.
 // real: real matrices (C planes; conj then means transpose)
+// urgent: the solve is on the factorisation's critical path (the next panel's columns);
+// its waves raise their issue priority over work of the other stream sharing their CUs
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
                        ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s,
-                       const int32_t *swl = nullptr, int swstride = 0, bool real = false);
+                       const int32_t *swl = nullptr, int swstride = 0, bool real = false,
+                       bool urgent = false);
 
 // Cm := beta Cm + alpha op(A) op(B);  method 0 = 4M, 1 = 3M, 2 = real (only the real
 // planes of A, B and Cm are read, only those of Cm written; 'C' acts as 'T')
+// urgent: as for launch_trsm
 hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,
                        int alpha_sign, ZM A, int64_t ai, int64_t aj, ZM B, int64_t bi,
-                       int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s);
+                       int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s,
+                       bool urgent = false);
 
 // split products (Ozaki scheme) for the 3M form: digits on INT8 (i8) or FP64 MFMA; S = 0
 // selects the default slice count

@@ -26,6 +26,7 @@ struct GemmArgs {
   int64_t m, n, k;
   int opA, opB;  // 'N', 'T', 'C'
   int alpha, beta;
+  int urgent;  // raise the waves' issue priority (critical-path product)
 };
 
 // Products deeper than TIDY_MIN_K (never the trailing updates of the factorisation, whose
@@ -52,6 +53,7 @@ constexpr int gemm_min_waves() {
 template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR, bool RE = false>
 __global__ __launch_bounds__((BM / TM) * (BN / TN), (gemm_min_waves<C, M3, BM, BN, BK, UNR, RE>()))
 void k_gemm(GemmArgs g) {
+  if (g.urgent) __builtin_amdgcn_s_setprio(2);
   constexpr int NT = (BM / TM) * (BN / TN);
   constexpr int NV = RE ? 1 : (M3 ? 3 : 2);
   constexpr int SX = BN / TN;  // threads along n
@@ -98,8 +100,13 @@ void k_gemm(GemmArgs g) {
   const double asign = (!M3 && !RE && g.alpha < 0) ? -1.0 : 1.0;
 
   for (int64_t k0 = 0; k0 < g.k; k0 += BK) {
+    // the staging addresses are recomputed for every slab from an opaque copy of the
+    // thread index: kept live across the k loop instead, they would be spilled to scratch
+    // at the register budget the launch bounds ask for
+    int tids = tid;
+    if (gemm_min_waves<C, M3, BM, BN, BK, UNR, RE>() > 1) asm volatile("" : "+v"(tids));
     // stage op(A)[m0 .. m0+BM) x [k0 .. k0+BK)
-    for (int e = tid; e < BM * BK; e += NT) {
+    for (int e = tids; e < BM * BK; e += NT) {
       int mm, kk;
       if (g.opA == 'N') { mm = e % BM; kk = e / BM; }
       else { kk = e % BK; mm = e / BK; }
@@ -133,7 +140,7 @@ void k_gemm(GemmArgs g) {
       }
     }
     // stage op(B)[k0 .. k0+BK) x [n0 .. n0+BN)
-    for (int e = tid; e < BN * BK; e += NT) {
+    for (int e = tids; e < BN * BK; e += NT) {
       int nn, kk;
       if (g.opB == 'N') { kk = e % BK; nn = e / BK; }
       else { nn = e % BN; kk = e / BN; }
@@ -396,7 +403,8 @@ static int gemm_cfg() {
 
 hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t n, int64_t k,
                        int alpha_sign, ZM A, int64_t ai, int64_t aj, ZM B, int64_t bi,
-                       int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s) {
+                       int64_t bj, int beta, ZM Cm, int64_t ci, int64_t cj, hipStream_t s,
+                       bool urgent) {
   if (m <= 0 || n <= 0) return hipSuccess;
   GemmArgs a;
   a.A = A; a.B = B; a.Cm = Cm;
@@ -404,6 +412,7 @@ hipError_t launch_gemm(int C, int method, char opA, char opB, int64_t m, int64_t
   a.m = m; a.n = n; a.k = k;
   a.opA = opA; a.opB = opB;
   a.alpha = alpha_sign; a.beta = beta;
+  a.urgent = urgent ? 1 : 0;
   const bool m3 = (method == 1);
   // products too small to give each CU a few 32 x 32 tiles (the next panel's columns in
   // the look-ahead, the last trailing updates) take 16 x 16 tiles, one element per

@@ -23,6 +23,7 @@ struct TrsmArgs {
   // destination rows at swl + 1, source rows at swl + 1 + swstride (absolute rows of X)
   const int32_t *swl;
   int swstride;
+  int urgent;  // raise the waves' issue priority (critical-path solve)
 };
 
 // op(T)[r][i]; RE: a real matrix (C planes), op = transpose when CONJ, im returned zero
@@ -61,6 +62,7 @@ __device__ __forceinline__ double wbcast(double v, int s) {
 template <int C, bool LOWER, bool UNIT, bool CONJ, int TW, bool RE>
 __global__ __launch_bounds__(256) void k_trsm(TrsmArgs a) {
   extern __shared__ double smem[];
+  if (a.urgent) __builtin_amdgcn_s_setprio(2);
   constexpr int Q = RE ? C : 2 * C;
   // TW: columns per wave in flight (more hides latency, fewer spreads a narrow strip)
   const int nb = a.nb, NBC = a.nbc, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -270,7 +272,7 @@ static hipError_t dispatch(bool lower, bool unit, bool conj, const TrsmArgs &a, 
 
 hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t0, int nb,
                        ZM Xm, int64_t x0, int64_t c0, int64_t ncols, hipStream_t s,
-                       const int32_t *swl, int swstride, bool real) {
+                       const int32_t *swl, int swstride, bool real, bool urgent) {
   if (nb <= 0 || ncols <= 0) return hipSuccess;
   if (nb > 64) {
     if (swl) {
@@ -315,6 +317,7 @@ hipError_t launch_trsm(int C, bool lower, bool unit, bool conj, ZM Tm, int64_t t
   a.ncols = ncols;
   a.swl = swl;
   a.swstride = swstride;
+  a.urgent = urgent ? 1 : 0;
   // columns per workgroup: a multiple of the 8 the four waves take per pass (two columns
   // each), enough to spread over about 512 workgroups (two per CU for double-double);
   // strips of at most 256 columns take 4 columns per workgroup, one per wave
