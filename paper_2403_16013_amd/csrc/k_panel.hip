@@ -368,9 +368,29 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
   int *sPivRow = sRedI + 4;                      // [kb]
   int *sList = sPivRow + kb;                     // [4 kb]
 
-  for (int e = t; e < nr * kb * Q; e += PNT) {
-    const int r = e % nr, rest = e / nr, c = rest % kb, q = rest / kb;
-    SA(c, q, r) = A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)];
+  {
+    // the panel's rows into LDS: thread t takes row t % nr and every P-th (column, plane)
+    // pair from t / nr (P = PNT / nr threads per row), sixteen loads in flight before
+    // their stores (one at a time would wait out a memory round trip per element)
+    constexpr int LB = 16;
+    const int P = nr > 0 ? PNT / nr : 0;
+    if (nr > 0 && t < P * nr) {
+      const int r = t % nr;
+      const double *src = A.p + j + r0 + r;
+      for (int cq0 = t / nr; cq0 < kb * Q; cq0 += LB * P) {
+        double v[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int cq = cq0 + u * P;  // (column, plane) = (cq / Q, cq % Q)
+          if (cq < kb * Q) v[u] = src[(int64_t)(cq % Q) * A.ps + (j + cq / Q) * A.ld];
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int cq = cq0 + u * P;
+          if (cq < kb * Q) sA[(size_t)cq * R + r] = v[u];  // SA(cq / Q, cq % Q, r)
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -676,9 +696,27 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
     __syncthreads();
   }
 
-  for (int e = t; e < nr * kb * Q; e += PNT) {
-    const int r = e % nr, rest = e / nr, c = rest % kb, q = rest / kb;
-    A.p[(int64_t)q * A.ps + (j + c) * A.ld + (j + r0 + r)] = SA(c, q, r);
+  {
+    // write-back with the load's thread mapping, sixteen LDS reads ahead of their stores
+    constexpr int LB = 16;
+    const int P = nr > 0 ? PNT / nr : 0;
+    if (nr > 0 && t < P * nr) {
+      const int r = t % nr;
+      double *dst = A.p + j + r0 + r;
+      for (int cq0 = t / nr; cq0 < kb * Q; cq0 += LB * P) {
+        double v[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int cq = cq0 + u * P;
+          if (cq < kb * Q) v[u] = sA[(size_t)cq * R + r];
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int cq = cq0 + u * P;
+          if (cq < kb * Q) dst[(int64_t)(cq % Q) * A.ps + (j + cq / Q) * A.ld] = v[u];
+        }
+      }
+    }
   }
 
   // workgroup 0: the interchange list for the columns outside the panel.  Replaying the
