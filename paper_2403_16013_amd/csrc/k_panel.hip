@@ -455,40 +455,46 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
 
     // (3) while the barrier is in flight: wave 1 inverts this workgroup's candidate pivot
     // (only the winner's reciprocal will be read, by every workgroup, with the pivot
-    // row); the other three waves apply the pending step k-1 update of columns > k
-    if (w == 1) {
-      if (lane == 0 && idx != INT_MAX) {
-        double pr[C], pi[C], rr[C], ri[C];
-        const int lr = (int)(idx - r0);
+    // row); waves 0, 2 and 3 apply the pending step k-1 update of columns > k, and for
+    // double-double, whose reciprocal is short, wave 1 takes the last eighth of the
+    // columns after it (DD 3M gesv 0.3-0.5 ms faster; neutral to slightly slower for TD
+    // and QD, where wave 1 stays out)
+    if (w == 1 && lane == 0 && idx != INT_MAX) {
+      double pr[C], pi[C], rr[C], ri[C];
+      const int lr = (int)(idx - r0);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          pr[c] = SA(k, c, lr);
-          pi[c] = RE ? 0.0 : SA(k, C + c, lr);
-        }
-        pv_recip<C, RE>(pr, pi, rr, ri);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          put(&rcpw[c * PGMAX + g], rr[c]);
-          if (!RE) put(&rcpw[(C + c) * PGMAX + g], ri[c]);
-        }
+      for (int c = 0; c < C; ++c) {
+        pr[c] = SA(k, c, lr);
+        pi[c] = RE ? 0.0 : SA(k, C + c, lr);
       }
-    } else if (!prev_zero && k + 1 < kb) {
+      pv_recip<C, RE>(pr, pi, rr, ri);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        put(&rcpw[c * PGMAX + g], rr[c]);
+        if (!RE) put(&rcpw[(C + c) * PGMAX + g], ri[c]);
+      }
+    }
+    if (!prev_zero && k + 1 < kb) {
       const int lo = (int)(k - r0 > 0 ? k - r0 : 0);  // rows with local index >= k
       const int cnt = nr - lo;
       const int ncol = kb - k - 1;
-      const int tot = cnt * ncol;
-      const int pt = (w == 0) ? t : t - 64;  // thread index among waves 0, 2 and 3
+      const int ncol1 = C == 2 ? ncol / 8 : 0;  // wave 1's columns
+      const int cb = (w == 1) ? k + 1 + (ncol - ncol1) : k + 1;
+      const int nc = (w == 1) ? ncol1 : ncol - ncol1;
+      const int tot = cnt * nc;
+      const int stride = (w == 1) ? 64 : PNT - 64;
+      const int pt = (w == 1) ? lane : ((w == 0) ? t : t - 64);  // index within the group
       // two elements per pass, both loaded before either is computed: their dependent
       // chains of FP64 operations interleave (a lone wave per SIMD otherwise waits out
       // each operation's latency; the wider formats spend most of a column here)
-      for (int e = pt; e < tot; e += 2 * (PNT - 64)) {
-        const bool two = e + (PNT - 64) < tot;
-        const int ee[2] = {e, two ? e + (PNT - 64) : e};
+      for (int e = pt; e < tot; e += 2 * stride) {
+        const bool two = e + stride < tot;
+        const int ee[2] = {e, two ? e + stride : e};
         double xr[2][C], xi[2][C], lr_[2][C], li[2][C], ur[2][C], ui[2][C];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int r = lo + ee[h] % cnt;
-          const int c = k + 1 + ee[h] / cnt;
+          const int c = cb + ee[h] / cnt;
 #pragma unroll
           for (int cc = 0; cc < C; ++cc) {
             xr[h][cc] = SA(c, cc, r);
@@ -506,7 +512,7 @@ __global__ __launch_bounds__(PNT) void k_panel(PanelArgs a) {
         for (int h = 0; h < 2; ++h) {
           if (h == 1 && !two) break;
           const int r = lo + ee[h] % cnt;
-          const int c = k + 1 + ee[h] / cnt;
+          const int c = cb + ee[h] / cnt;
 #pragma unroll
           for (int cc = 0; cc < C; ++cc) {
             SA(c, cc, r) = xr[h][cc];
