@@ -459,17 +459,30 @@ __global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
       v4d acc[S];
 #pragma unroll
       for (int l = 0; l < S; ++l) acc[l] = v4d{0.0, 0.0, 0.0, 0.0};
-      for (int64_t k4 = kb; k4 < kend; k4 += 4) {
-        double b[S];
+      // the next 4-deep step's digits are loaded while this step's MFMAs run (the last
+      // step reloads its own, in bounds and cached, instead of branching)
+      auto load = [&](int64_t k4, double (&a)[S], double (&b)[S]) {
 #pragma unroll
         for (int q = 0; q < S; ++q)
           b[q] = (bcol < g.n) ? ys[(((int64_t)op * S + q) * g.n + bcol) * g.Kpad + k4 + kl] : 0.0;
 #pragma unroll
-        for (int p = 0; p < S; ++p) {
-          const double a = (arow < g.m) ? xs[(((int64_t)op * S + p) * g.m + arow) * g.Kpad + k4 + kl] : 0.0;
+        for (int p = 0; p < S; ++p)
+          a[p] = (arow < g.m) ? xs[(((int64_t)op * S + p) * g.m + arow) * g.Kpad + k4 + kl] : 0.0;
+      };
+      double ac[S], bc[S];
+      load(kb, ac, bc);
+      for (int64_t k4 = kb; k4 < kend; k4 += 4) {
+        double an[S], bn[S];
+        load(k4 + 4 < kend ? k4 + 4 : k4, an, bn);
+#pragma unroll
+        for (int p = 0; p < S; ++p)
 #pragma unroll
           for (int q = 0; q < S - p; ++q)
-            acc[p + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[q], acc[p + q], 0, 0, 0);
+            acc[p + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[p], bc[q], acc[p + q], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          ac[i] = an[i];
+          bc[i] = bn[i];
         }
       }
 #pragma unroll
