@@ -506,6 +506,100 @@ __global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
   for (int e = 0; e < 4; ++e) epilogue<C, RE>(g, m0 + 4 * e + (lane >> 4), bcol, lr[e], li[e]);
 }
 
+// FP64 digits for double-double, staged in LDS: the four waves of a workgroup share each
+// 16-deep chunk of the digit planes of their 32 rows and 32 columns (loaded straight from
+// memory, every fragment was fetched by two waves and the fetches held the MFMAs back).
+// Piece t (16 bytes: two consecutive k) of a plane's chunk goes to LDS slot t, which is
+// element (step s, row r, k 4 s + kk) at ((s * 32 + r) * 4 + kk): a fragment read (16
+// rows x 4 k of one step) is then 64 consecutive doubles.  Two workgroups share a CU
+// (48 KB of planes each for S = 6), so one's MFMAs run while the other's chunk loads.
+template <int S, int NO>
+__global__ __launch_bounds__(256, 2) void k_split_f64_dd(SplitArgs g) {
+  constexpr int C = 2, W = 22, KC = 16;
+  constexpr int PL = 32 * KC / 2;  // 16-byte pieces per plane per chunk
+  constexpr bool RE = NO == 1;
+  extern __shared__ double sfd[];  // [2 operands][S planes][PL pieces of 2 doubles]
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t M0 = (int64_t)blockIdx.y * 32, N0 = (int64_t)blockIdx.x * 32;
+  const int64_t m0 = M0 + 16 * (w >> 1), n0 = N0 + 16 * (w & 1);
+  const int64_t bcol = n0 + (lane & 15);
+  const int kl = lane >> 4;
+  const int rA = 16 * (w >> 1) + (lane & 15), rB = 16 * (w & 1) + (lane & 15);
+  const double *xs = (const double *)g.xs, *ys = (const double *)g.ys;
+  // the piece this thread fetches in every plane and chunk: step t / 64, row (t / 2) % 32,
+  // k pair 2 (t % 2); rows and columns past the edge fetch the last valid one (they only
+  // reach outputs that are never stored)
+  const int fs = t >> 6, fr = (t >> 1) & 31, fk = 2 * (t & 1);
+  const int64_t gi = (M0 + fr < g.m) ? M0 + fr : g.m - 1;
+  const int64_t gj = (N0 + fr < g.n) ? N0 + fr : g.n - 1;
+  const double *px = xs + gi * g.Kpad + 4 * fs + fk;
+  const double *py = ys + gj * g.Kpad + 4 * fs + fk;
+  const int64_t psx = g.m * g.Kpad, psy = g.n * g.Kpad;  // plane strides
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  double lr[4][C], li[4][C];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
+
+  for (int op = 0; op < NO; ++op) {
+    double sr, si;
+    op_signs(op, sr, si);
+    if (RE) si = 0.0;
+    for (int64_t kb = 0; kb < g.Kpad; kb += 128) {
+      const int64_t kend = (kb + 128 < g.Kpad) ? kb + 128 : g.Kpad;
+      v4d acc[S];
+#pragma unroll
+      for (int l = 0; l < S; ++l) acc[l] = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int64_t kc = kb; kc < kend; kc += KC) {
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          __builtin_amdgcn_global_load_lds(
+              (const void *)(px + ((int64_t)op * S + p) * psx + kc),
+              (__attribute__((address_space(3))) void *)(sfd + ((size_t)p * PL + wu * 64) * 2),
+              16, 0, 0);
+          __builtin_amdgcn_global_load_lds(
+              (const void *)(py + ((int64_t)op * S + p) * psy + kc),
+              (__attribute__((address_space(3))) void *)(sfd + ((size_t)(S + p) * PL + wu * 64) * 2),
+              16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces have landed
+        __syncthreads();                // and everybody else's
+#pragma unroll
+        for (int st = 0; st < KC / 4; ++st) {
+          double a[S], b[S];
+#pragma unroll
+          for (int p = 0; p < S; ++p) {
+            a[p] = sfd[(size_t)p * PL * 2 + (st * 32 + rA) * 4 + kl];
+            b[p] = sfd[(size_t)(S + p) * PL * 2 + (st * 32 + rB) * 4 + kl];
+          }
+#pragma unroll
+          for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int q = 0; q < S - p; ++q)
+              acc[p + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc[p + q], 0, 0, 0);
+        }
+        __syncthreads();  // the buffer is refilled next
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t mi = m0 + 4 * e + (lane >> 4), nj = bcol;
+        const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
+                         (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
+#pragma unroll
+        for (int l = S - 1; l >= 0; --l) {
+          const int lvl = (l * W) / 53 < C - 1 ? (l * W) / 53 : C - 1;
+          const double v = ldexp(acc[l][e], tsum - (l + 2) * W);
+          if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * v);
+          if (!RE) mp::push<C>(li[e], lvl, si * v);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) epilogue<C, RE>(g, m0 + 4 * e + (lane >> 4), bcol, lr[e], li[e]);
+}
+
 // ------------------------------------------------------------------ host side
 static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -515,7 +609,7 @@ int split_slices(int C, bool i8) {
 }
 
 static inline int64_t kpad_of(int64_t K, bool i8) {
-  const int64_t q = i8 ? 64 : 4;
+  const int64_t q = i8 ? 64 : 16;  // the INT8 chunk, the FP64 double-double chunk
   return ((K + q - 1) / q) * q;
 }
 
@@ -576,7 +670,15 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_split_i8<C, S, NO>), grid1, dim3(256), lds, s, g);
   } else {
-    hipLaunchKernelGGL((k_split_f64<C, S, NO>), grid, dim3(256), 0, s, g);
+    if constexpr (C == 2) {
+      const size_t lds = sizeof(double) * 2 * 2 * S * (32 * 16 / 2);
+      static LdsAttr attr;
+      const hipError_t e = attr.ensure((const void *)k_split_f64_dd<S, NO>, (int)lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_split_f64_dd<S, NO>), grid, dim3(256), lds, s, g);
+    } else {
+      hipLaunchKernelGGL((k_split_f64<C, S, NO>), grid, dim3(256), 0, s, g);
+    }
   }
   return hipGetLastError();
 }
