@@ -434,90 +434,21 @@ __global__ __launch_bounds__(256) void k_split_i8(SplitArgs g) {
 
 // FP64 digits, W = 22, K processed in blocks of 128 (the exactness limit of one level).
 // D layout of the 16x16x4 FP64 MFMA: element (4 e + lane/16, lane % 16) in register e.
+// The digits are staged in LDS: the four waves of a workgroup share each 16-deep chunk of
+// the digit planes of their 32 rows and 32 columns (loaded straight from memory, every
+// fragment was fetched by two waves and the fetches held the MFMAs back).  Piece e (16
+// bytes: two consecutive k) of a plane's chunk goes to LDS slot e, which is element
+// (step s, row r, k 4 s + kk) at ((s * 32 + r) * 4 + kk): a fragment read (16 rows x 4 k
+// of one step) is 64 consecutive doubles.
+//   DD: the pieces go straight to LDS (48 KB for S = 6); two workgroups share a CU, so
+//       one's MFMAs run while the other's chunk loads.
+//   TD, QD (72 and 88 KB, one workgroup per CU): the next chunk's pieces are loaded into
+//       registers while this chunk's MFMAs run and written to LDS after them.
 template <int C, int S, int NO>
-__global__ __launch_bounds__(256) void k_split_f64(SplitArgs g) {
-  constexpr int W = 22;
-  constexpr bool RE = NO == 1;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t m0 = (int64_t)blockIdx.y * 32 + 16 * (w >> 1);
-  const int64_t n0 = (int64_t)blockIdx.x * 32 + 16 * (w & 1);
-  const int64_t arow = m0 + (lane & 15), bcol = n0 + (lane & 15);
-  const int64_t kl = lane >> 4;
-  const double *xs = (const double *)g.xs, *ys = (const double *)g.ys;
-  double lr[4][C], li[4][C];
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-#pragma unroll
-    for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
-
-  for (int op = 0; op < NO; ++op) {
-    double sr, si;
-    op_signs(op, sr, si);
-    if (RE) si = 0.0;
-    for (int64_t kb = 0; kb < g.Kpad; kb += 128) {
-      const int64_t kend = (kb + 128 < g.Kpad) ? kb + 128 : g.Kpad;
-      v4d acc[S];
-#pragma unroll
-      for (int l = 0; l < S; ++l) acc[l] = v4d{0.0, 0.0, 0.0, 0.0};
-      // the next 4-deep step's digits are loaded while this step's MFMAs run (the last
-      // step reloads its own, in bounds and cached, instead of branching)
-      auto load = [&](int64_t k4, double (&a)[S], double (&b)[S]) {
-#pragma unroll
-        for (int q = 0; q < S; ++q)
-          b[q] = (bcol < g.n) ? ys[(((int64_t)op * S + q) * g.n + bcol) * g.Kpad + k4 + kl] : 0.0;
-#pragma unroll
-        for (int p = 0; p < S; ++p)
-          a[p] = (arow < g.m) ? xs[(((int64_t)op * S + p) * g.m + arow) * g.Kpad + k4 + kl] : 0.0;
-      };
-      double ac[S], bc[S];
-      load(kb, ac, bc);
-      for (int64_t k4 = kb; k4 < kend; k4 += 4) {
-        double an[S], bn[S];
-        load(k4 + 4 < kend ? k4 + 4 : k4, an, bn);
-#pragma unroll
-        for (int p = 0; p < S; ++p)
-#pragma unroll
-          for (int q = 0; q < S - p; ++q)
-            acc[p + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[p], bc[q], acc[p + q], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-          ac[i] = an[i];
-          bc[i] = bn[i];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t mi = m0 + 4 * e + (lane >> 4), nj = bcol;
-        const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
-                         (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
-#pragma unroll
-        for (int l = S - 1; l >= 0; --l) {
-          // level l is at most 2^(-l W) of the largest possible level-0 sum: it enters the
-          // accumulator at component level l W / 53 (as in k_split_i8)
-          const int lvl = (l * W) / 53 < C - 1 ? (l * W) / 53 : C - 1;
-          const double v = ldexp(acc[l][e], tsum - (l + 2) * W);
-          if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * v);
-          if (!RE) mp::push<C>(li[e], lvl, si * v);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) epilogue<C, RE>(g, m0 + 4 * e + (lane >> 4), bcol, lr[e], li[e]);
-}
-
-// FP64 digits for double-double, staged in LDS: the four waves of a workgroup share each
-// 16-deep chunk of the digit planes of their 32 rows and 32 columns (loaded straight from
-// memory, every fragment was fetched by two waves and the fetches held the MFMAs back).
-// Piece t (16 bytes: two consecutive k) of a plane's chunk goes to LDS slot t, which is
-// element (step s, row r, k 4 s + kk) at ((s * 32 + r) * 4 + kk): a fragment read (16
-// rows x 4 k of one step) is then 64 consecutive doubles.  Two workgroups share a CU
-// (48 KB of planes each for S = 6), so one's MFMAs run while the other's chunk loads.
-template <int S, int NO>
-__global__ __launch_bounds__(256, 2) void k_split_f64_dd(SplitArgs g) {
-  constexpr int C = 2, W = 22, KC = 16;
-  constexpr int PL = 32 * KC / 2;  // 16-byte pieces per plane per chunk
-  constexpr bool RE = NO == 1;
+__global__ __launch_bounds__(256, C == 2 ? 2 : 1) void k_split_f64_lds(SplitArgs g) {
+  constexpr int W = 22, KC = 16, PL = 32 * KC / 2;  // 16-byte pieces per plane per chunk
+  constexpr bool RE = NO == 1, DMA = C == 2;
+  typedef double v2d __attribute__((ext_vector_type(2)));
   extern __shared__ double sfd[];  // [2 operands][S planes][PL pieces of 2 doubles]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t M0 = (int64_t)blockIdx.y * 32, N0 = (int64_t)blockIdx.x * 32;
@@ -526,6 +457,7 @@ __global__ __launch_bounds__(256, 2) void k_split_f64_dd(SplitArgs g) {
   const int kl = lane >> 4;
   const int rA = 16 * (w >> 1) + (lane & 15), rB = 16 * (w & 1) + (lane & 15);
   const double *xs = (const double *)g.xs, *ys = (const double *)g.ys;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
   // the piece this thread fetches in every plane and chunk: step t / 64, row (t / 2) % 32,
   // k pair 2 (t % 2); rows and columns past the edge fetch the last valid one (they only
   // reach outputs that are never stored)
@@ -535,13 +467,39 @@ __global__ __launch_bounds__(256, 2) void k_split_f64_dd(SplitArgs g) {
   const double *px = xs + gi * g.Kpad + 4 * fs + fk;
   const double *py = ys + gj * g.Kpad + 4 * fs + fk;
   const int64_t psx = g.m * g.Kpad, psy = g.n * g.Kpad;  // plane strides
-  const int wu = __builtin_amdgcn_readfirstlane(w);
+  v2d rx[S], ry[S];  // register staging (TD, QD)
+  auto fetch = [&](int op, int64_t kc) {
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      if (DMA) {
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(px + ((int64_t)op * S + p) * psx + kc),
+            (__attribute__((address_space(3))) void *)(sfd + ((size_t)p * PL + wu * 64) * 2), 16,
+            0, 0);
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(py + ((int64_t)op * S + p) * psy + kc),
+            (__attribute__((address_space(3))) void *)(sfd + ((size_t)(S + p) * PL + wu * 64) * 2),
+            16, 0, 0);
+      } else {
+        rx[p] = *(const v2d *)(px + ((int64_t)op * S + p) * psx + kc);
+        ry[p] = *(const v2d *)(py + ((int64_t)op * S + p) * psy + kc);
+      }
+    }
+  };
+  auto store = [&]() {  // register staging into LDS
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      *(v2d *)(sfd + ((size_t)p * PL + t) * 2) = rx[p];
+      *(v2d *)(sfd + ((size_t)(S + p) * PL + t) * 2) = ry[p];
+    }
+  };
   double lr[4][C], li[4][C];
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int c = 0; c < C; ++c) { lr[e][c] = 0.0; li[e][c] = 0.0; }
+    for (int c = 0; c < C; ++c) { lr[q][c] = 0.0; li[q][c] = 0.0; }
 
+  if (!DMA) fetch(0, 0);
   for (int op = 0; op < NO; ++op) {
     double sr, si;
     op_signs(op, sr, si);
@@ -551,20 +509,23 @@ __global__ __launch_bounds__(256, 2) void k_split_f64_dd(SplitArgs g) {
       v4d acc[S];
 #pragma unroll
       for (int l = 0; l < S; ++l) acc[l] = v4d{0.0, 0.0, 0.0, 0.0};
+      if (DMA) fetch(op, kb);
       for (int64_t kc = kb; kc < kend; kc += KC) {
-#pragma unroll
-        for (int p = 0; p < S; ++p) {
-          __builtin_amdgcn_global_load_lds(
-              (const void *)(px + ((int64_t)op * S + p) * psx + kc),
-              (__attribute__((address_space(3))) void *)(sfd + ((size_t)p * PL + wu * 64) * 2),
-              16, 0, 0);
-          __builtin_amdgcn_global_load_lds(
-              (const void *)(py + ((int64_t)op * S + p) * psy + kc),
-              (__attribute__((address_space(3))) void *)(sfd + ((size_t)(S + p) * PL + wu * 64) * 2),
-              16, 0, 0);
+        if (DMA) {
+          __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces have landed
+        } else {
+          store();
+          // the next chunk (of this block, else of the next block or product) is fetched
+          // into the registers while this one is multiplied
+          int64_t nk = kc + KC;
+          int nop = op;
+          if (nk >= kend) {
+            nk = kend;
+            if (nk >= g.Kpad) { nk = 0; ++nop; }
+          }
+          if (nop < NO) fetch(nop, nk);
         }
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's pieces have landed
-        __syncthreads();                // and everybody else's
+        __syncthreads();  // every wave's pieces are in LDS
 #pragma unroll
         for (int st = 0; st < KC / 4; ++st) {
           double a[S], b[S];
@@ -580,24 +541,25 @@ __global__ __launch_bounds__(256, 2) void k_split_f64_dd(SplitArgs g) {
               acc[p + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], b[q], acc[p + q], 0, 0, 0);
         }
         __syncthreads();  // the buffer is refilled next
+        if (DMA && kc + KC < kend) fetch(op, kc + KC);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t mi = m0 + 4 * e + (lane >> 4), nj = bcol;
+      for (int q = 0; q < 4; ++q) {
+        const int64_t mi = m0 + 4 * q + (lane >> 4), nj = bcol;
         const int tsum = (mi < g.m ? g.tx[(int64_t)op * g.m + mi] : 0) +
                          (nj < g.n ? g.ty[(int64_t)op * g.n + nj] : 0);
 #pragma unroll
         for (int l = S - 1; l >= 0; --l) {
           const int lvl = (l * W) / 53 < C - 1 ? (l * W) / 53 : C - 1;
-          const double v = ldexp(acc[l][e], tsum - (l + 2) * W);
-          if (sr != 0.0) mp::push<C>(lr[e], lvl, sr * v);
-          if (!RE) mp::push<C>(li[e], lvl, si * v);
+          const double v = ldexp(acc[l][q], tsum - (l + 2) * W);
+          if (sr != 0.0) mp::push<C>(lr[q], lvl, sr * v);
+          if (!RE) mp::push<C>(li[q], lvl, si * v);
         }
       }
     }
   }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) epilogue<C, RE>(g, m0 + 4 * e + (lane >> 4), bcol, lr[e], li[e]);
+  for (int q = 0; q < 4; ++q) epilogue<C, RE>(g, m0 + 4 * q + (lane >> 4), bcol, lr[q], li[q]);
 }
 
 // ------------------------------------------------------------------ host side
@@ -670,15 +632,11 @@ static hipError_t run(char opA, char opB, int64_t m, int64_t n, int64_t k, int a
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_split_i8<C, S, NO>), grid1, dim3(256), lds, s, g);
   } else {
-    if constexpr (C == 2) {
-      const size_t lds = sizeof(double) * 2 * 2 * S * (32 * 16 / 2);
-      static LdsAttr attr;
-      const hipError_t e = attr.ensure((const void *)k_split_f64_dd<S, NO>, (int)lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_split_f64_dd<S, NO>), grid, dim3(256), lds, s, g);
-    } else {
-      hipLaunchKernelGGL((k_split_f64<C, S, NO>), grid, dim3(256), 0, s, g);
-    }
+    const size_t lds = sizeof(double) * 2 * 2 * S * (32 * 16 / 2);
+    static LdsAttr attr;
+    const hipError_t e = attr.ensure((const void *)k_split_f64_lds<C, S, NO>, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_split_f64_lds<C, S, NO>), grid, dim3(256), lds, s, g);
   }
   return hipGetLastError();
 }
