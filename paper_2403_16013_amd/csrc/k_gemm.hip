@@ -50,7 +50,30 @@ constexpr int gemm_min_waves() {
   return C == 2 ? (UNR == 2 ? 4 : 1) : (C == 3 ? 3 : 1);
 }
 
-template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR, bool RE = false>
+// The double-double MAC of mp::mac without its two cross products a_hi b_lo + a_lo b_hi:
+// TwoProd of the leading parts, its product into level 0 by TwoSum, both errors into
+// level 1 (10 instructions instead of 12).  The cross products, needed to binary64
+// accuracy only (level-1 terms), are summed separately on the FP64 matrix cores.
+__device__ __forceinline__ void mac_dd_lead(double (&l)[2], const double (&a)[2],
+                                            const double (&b)[2]) {
+  double p, e, s, t;
+  mp::two_prod(a[0], b[0], p, e);
+  mp::two_sum(l[0], p, s, t);
+  l[0] = s;
+  l[1] += t;
+  l[1] += e;
+}
+
+// XM: double-double 3M or real products of depth <= TIDY_MIN_K with the cross products on
+// v_mfma_f64_16x16x4f64.  Every 16 x 16 block of the output is summed over k in the same
+// 4-deep steps, (a_hi b_lo) then (a_lo b_hi) in each, in both tilings: in 32 x 32 tiles
+// each wave owns one 16 x 16 quarter for all NV products; in 16 x 16 tiles wave v owns
+// product v.  The sums reach level 1 of the accumulators once, after the last step of k.
+// On this GPU the FP64 matrix rate equals the vector rate, so the gain is the issue slots
+// of the two FMAs (first trailing update at n = 4096, K = 64: 1.75 -> 1.68 ms; four waves
+// per SIMD, one cross accumulator saved to scratch once per slab, beat three without).
+template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR, bool RE = false,
+          bool XM = false>
 __global__ __launch_bounds__((BM / TM) * (BN / TN), (gemm_min_waves<C, M3, BM, BN, BK, UNR, RE>()))
 void k_gemm(GemmArgs g) {
   if (g.urgent) __builtin_amdgcn_s_setprio(2);
@@ -59,8 +82,18 @@ void k_gemm(GemmArgs g) {
   constexpr int SX = BN / TN;  // threads along n
   constexpr int SY = BM / TM;  // threads along m
   static_assert(TIDY_K % BK == 0, "re-levelling points must fall on slab ends");
+  static_assert(!XM || (C == 2 && (M3 || RE) && NT == 256 && BK % 4 == 0 &&
+                        ((BM == 32 && BN == 32) || (BM == 16 && BN == 16))),
+                "cross products on the matrix cores: double-double 3M / real, 16 or 32 tiles");
   __shared__ double sA[BK][NV][C][BM];
   __shared__ double sB[BK][NV][C][BN];
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  // 16 x 16 blocks per wave and their products: 32 x 32 tiles, quarter w, all NV
+  // products; 16 x 16 tiles, wave v < NV, product v
+  constexpr int XN = (BM == 32) ? NV : 1;
+  v4d xacc[XN];
+#pragma unroll
+  for (int q = 0; q < XN; ++q) xacc[q] = v4d{0.0, 0.0, 0.0, 0.0};
 
   const int tid = threadIdx.x;
   const int tx = tid % SX, ty = tid / SX;
@@ -176,6 +209,25 @@ void k_gemm(GemmArgs g) {
     }
     __syncthreads();
 
+    if constexpr (XM) {
+      const int w = tid >> 6, lane = tid & 63;
+      const int xr = (BM == 32) ? 16 * (w >> 1) : 0, xc = (BM == 32) ? 16 * (w & 1) : 0;
+      if (BM == 32 || w < NV) {
+#pragma unroll
+        for (int st = 0; st < BK / 4; ++st) {
+          const int kq = 4 * st + (lane >> 4);
+#pragma unroll
+          for (int q = 0; q < XN; ++q) {
+            const int v = (BM == 32) ? q : w;
+            const double ah = sA[kq][v][0][xr + (lane & 15)], al = sA[kq][v][1][xr + (lane & 15)];
+            const double bh = sB[kq][v][0][xc + (lane & 15)], bl = sB[kq][v][1][xc + (lane & 15)];
+            xacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ah, bl, xacc[q], 0, 0, 0);
+            xacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(al, bh, xacc[q], 0, 0, 0);
+          }
+        }
+      }
+    }
+
 #pragma unroll UNR
     for (int kk = 0; kk < BK; ++kk) {
       double a[NV][TM][C], b[NV][TN][C];
@@ -190,7 +242,14 @@ void k_gemm(GemmArgs g) {
 #pragma unroll
           for (int c = 0; c < C; ++c) b[v][jj][c] = sB[kk][v][c][tx + jj * SX];
       }
-      if (RE) {
+      if constexpr (XM) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int jj = 0; jj < TN; ++jj)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) mac_dd_lead(acc[v][i][jj], a[v][i], b[v][jj]);
+      } else if (RE) {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -232,6 +291,34 @@ void k_gemm(GemmArgs g) {
           for (int jj = 0; jj < TN; ++jj) mp::tidy<C>(acc[v][i][jj]);
     }
     __syncthreads();
+  }
+
+  if constexpr (XM) {
+    // the cross sums to level 1 of their elements' accumulators, through LDS (the staging
+    // buffers, free after the last slab): X[v][row][col] at v BM BN + row BN + col
+    constexpr int NA = BK * NV * C * BM;
+    static_assert(NA + BK * NV * C * BN >= NV * BM * BN, "exchange fits the staging buffers");
+    double *fa = &sA[0][0][0][0], *fb = &sB[0][0][0][0];
+    auto X = [&](int idx) -> double & { return idx < NA ? fa[idx] : fb[idx - NA]; };
+    const int w = tid >> 6, lane = tid & 63;
+    const int xr = (BM == 32) ? 16 * (w >> 1) : 0, xc = (BM == 32) ? 16 * (w & 1) : 0;
+    if (BM == 32 || w < NV) {
+#pragma unroll
+      for (int q = 0; q < XN; ++q) {
+        const int v = (BM == 32) ? q : w;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          X(v * BM * BN + (xr + 4 * e + (lane >> 4)) * BN + xc + (lane & 15)) = xacc[q][e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < TN; ++jj)
+          acc[v][i][jj][1] += X(v * BM * BN + (ty + i * SY) * BN + tx + jj * SX);
   }
 
   // epilogue
@@ -371,7 +458,14 @@ template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR, bool 
 static hipError_t go(const GemmArgs &a, hipStream_t s) {
   constexpr int NT = (BM / TM) * (BN / TN);
   const dim3 grid((unsigned)(((a.n + BN - 1) / BN) * ((a.m + BM - 1) / BM)));
-  hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN, UNR, RE>), grid, dim3(NT), 0, s, a);
+  // double-double 3M and real products of trailing-update depth: cross products on the
+  // matrix cores (both tile sizes, so that the tiling never changes a result)
+  constexpr bool XMOK = C == 2 && (M3 || RE) && NT == 256 &&
+                        ((BM == 32 && BN == 32) || (BM == 16 && BN == 16));
+  if (XMOK && a.k <= TIDY_MIN_K)
+    hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN, UNR, RE, XMOK>), grid, dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_gemm<C, M3, BM, BN, BK, TM, TN, UNR, RE>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
