@@ -44,9 +44,10 @@ constexpr int64_t TIDY_MIN_K = 128;
 // scratch and are reloaded once per staged slab, never inside the k loop; measured 1-4%
 // faster on the trailing update than the three and two waves the register use would
 // otherwise give.  Quadruple-double stays at two (three would spill inside the k loop).
-template <int C, bool M3, int BM, int BN, int BK, int UNR, bool RE>
+template <int C, bool M3, int BM, int BN, int BK, int UNR, bool RE, bool XM = false>
 constexpr int gemm_min_waves() {
   if (BM != 32 || BN != 32 || BK != 8 || RE || !M3) return 1;
+  if (XM) return 3;  // the MFMA cross accumulators need 10 more registers
   return C == 2 ? (UNR == 2 ? 4 : 1) : (C == 3 ? 3 : 1);
 }
 
@@ -70,11 +71,12 @@ __device__ __forceinline__ void mac_dd_lead(double (&l)[2], const double (&a)[2]
 // each wave owns one 16 x 16 quarter for all NV products; in 16 x 16 tiles wave v owns
 // product v.  The sums reach level 1 of the accumulators once, after the last step of k.
 // On this GPU the FP64 matrix rate equals the vector rate, so the gain is the issue slots
-// of the two FMAs (first trailing update at n = 4096, K = 64: 1.75 -> 1.68 ms; four waves
-// per SIMD, one cross accumulator saved to scratch once per slab, beat three without).
+// of the two FMAs (first trailing update at n = 4096, K = 64: 1.75 -> 1.70 ms).  The 32 x 32
+// tiles run three waves per SIMD: at four, a cross accumulator went to scratch for every
+// slab (1% faster, but 60% more bytes written to memory).
 template <int C, bool M3, int BM, int BN, int BK, int TM, int TN, int UNR, bool RE = false,
           bool XM = false>
-__global__ __launch_bounds__((BM / TM) * (BN / TN), (gemm_min_waves<C, M3, BM, BN, BK, UNR, RE>()))
+__global__ __launch_bounds__((BM / TM) * (BN / TN), (gemm_min_waves<C, M3, BM, BN, BK, UNR, RE, XM>()))
 void k_gemm(GemmArgs g) {
   if (g.urgent) __builtin_amdgcn_s_setprio(2);
   constexpr int NT = (BM / TM) * (BN / TN);
@@ -137,7 +139,7 @@ void k_gemm(GemmArgs g) {
     // thread index: kept live across the k loop instead, they would be spilled to scratch
     // at the register budget the launch bounds ask for
     int tids = tid;
-    if (gemm_min_waves<C, M3, BM, BN, BK, UNR, RE>() > 1) asm volatile("" : "+v"(tids));
+    if (gemm_min_waves<C, M3, BM, BN, BK, UNR, RE, XM>() > 1) asm volatile("" : "+v"(tids));
     // stage op(A)[m0 .. m0+BM) x [k0 .. k0+BK)
     for (int e = tids; e < BM * BK; e += NT) {
       int mm, kk;
