@@ -570,6 +570,44 @@ def test_long_product_independent_of_tiling(mp, orc, C, method):
         assert np.array_equal(small, big[:, :, c0:c0 + nc, r0:r0 + mr])
 
 
+@pytest.mark.parametrize("C", CS)
+@pytest.mark.parametrize("k", [64, 100])
+def test_trailing_depth_product_independent_of_tiling(mp, orc, C, k):
+    """At trailing-update depths (k <= 128) the double-double 3M and real products sum
+    their cross products a_hi b_lo + a_lo b_hi on the FP64 matrix cores in the same 4-deep
+    steps in both tilings: a block of a large product (32 x 32 tiles) equals the same
+    block computed alone (16 x 16 tiles) bit for bit, for every format, also for a depth
+    that is not a multiple of the staging depth, and in the real product."""
+    import torch
+
+    m = n = 720   # 23 x 23 = 529 tiles of 32 x 32: the large-product kernel
+    A = orc.canon(synthgen.uniform(m, k, C, 130))
+    B = orc.canon(synthgen.uniform(k, n, C, 131))
+    Cm = orc.canon(synthgen.uniform(m, n, C, 132))
+    big = to_host(mp.gemm(to_dev(A), to_dev(B), to_dev(Cm), alpha=-1, method="3m"))
+    bigr = to_host(mp.dgemm(to_dev(A[0]), to_dev(B[0]), to_dev(Cm[0]), alpha=-1))
+    for (r0, c0, mr, nc) in ((37, 101, 90, 70), (500, 3, 64, 12), (0, 700, 720, 20)):
+        As = np.ascontiguousarray(A[:, :, :, r0:r0 + mr])
+        Bs = np.ascontiguousarray(B[:, :, c0:c0 + nc, :])
+        Cs = np.ascontiguousarray(Cm[:, :, c0:c0 + nc, r0:r0 + mr])
+        small = to_host(mp.gemm(torch.from_numpy(As).cuda(), torch.from_numpy(Bs).cuda(),
+                                torch.from_numpy(Cs).cuda(), alpha=-1, method="3m"))
+        assert np.array_equal(small, big[:, :, c0:c0 + nc, r0:r0 + mr])
+        smallr = to_host(mp.dgemm(torch.from_numpy(np.ascontiguousarray(As[0])).cuda(),
+                                  torch.from_numpy(np.ascontiguousarray(Bs[0])).cuda(),
+                                  torch.from_numpy(np.ascontiguousarray(Cs[0])).cuda(), alpha=-1))
+        assert np.array_equal(smallr, bigr[:, c0:c0 + nc, r0:r0 + mr])
+    # the real product is the real part of the complex 3M product on real data
+    def embed(R):
+        Z = np.zeros((2,) + R.shape)
+        Z[0] = R
+        return Z
+    z = to_host(mp.gemm(to_dev(embed(A[0])), to_dev(embed(B[0])), to_dev(embed(Cm[0])),
+                        alpha=-1, method="3m"))
+    assert np.array_equal(z[0], bigr)
+    assert not np.any(z[1])
+
+
 def test_solve_api_and_singular_check(mp, orc):
     """lu_factor / lu_solve leave their inputs alone and agree with gesv; solve with
     check_errors raises on an exactly singular matrix with and without autograd."""
