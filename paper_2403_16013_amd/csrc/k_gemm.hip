@@ -4,7 +4,8 @@
 // update A22 -= L21 U12 of the blocked LU (Sec. 3), where nearly all the time goes.
 //
 // Design for gfx950: the product is bound by FP64 vector arithmetic (each complex MAC is
-// 36 (3M, DD) to ~350 (3M, QD) FP64 instructions), so the kernel is a classic LDS-tiled
+// 36 (3M, DD; 30 when its cross products run on the matrix cores, see XM below) to ~350
+// (3M, QD) FP64 instructions), so the kernel is a classic LDS-tiled
 // register-blocked GEMM: a workgroup owns a BM x BN output tile, stages BK-deep slabs of
 // op(A) and op(B) in LDS (for 3M together with the rounded sums Re+Im of Eq. 3m_cemm,
 // computed once per staged element), and each thread accumulates a TM x TN micro-tile in
@@ -39,11 +40,13 @@ constexpr int64_t TIDY_MIN_K = 128;
 
 // RE: the real product (the Im = 0 case of the 3M form: only T1 = ReA ReB is formed,
 // only the real planes are read and written; the imaginary planes are never touched).
-// Waves per SIMD asked of the compiler for the 32 x 32 3M tiles: four for double-double
-// (128 registers) and three for triple-double, where a few address values then live in
-// scratch and are reloaded once per staged slab, never inside the k loop; measured 1-4%
-// faster on the trailing update than the three and two waves the register use would
-// otherwise give.  Quadruple-double stays at two (three would spill inside the k loop).
+// Waves per SIMD asked of the compiler for the 32 x 32 3M tiles: three for double-double
+// with the cross products on the matrix cores (XM, every trailing update) and four
+// without them (longer products, 128 registers); three for triple-double, where a few
+// address values then live in scratch and are reloaded once per staged slab, never inside
+// the k loop.  Measured 1-4% faster on the trailing update than the waves the register use
+// would otherwise give.  Quadruple-double stays at two (three would spill inside the k
+// loop).
 template <int C, bool M3, int BM, int BN, int BK, int UNR, bool RE, bool XM = false>
 constexpr int gemm_min_waves() {
   if (BM != 32 || BN != 32 || BK != 8 || RE || !M3) return 1;
