@@ -571,13 +571,14 @@ def test_long_product_independent_of_tiling(mp, orc, C, method):
 
 
 @pytest.mark.parametrize("C", CS)
-@pytest.mark.parametrize("k", [64, 100])
+@pytest.mark.parametrize("k", [37, 64, 100])
 def test_trailing_depth_product_independent_of_tiling(mp, orc, C, k):
     """At trailing-update depths (k <= 128) the double-double 3M and real products sum
     their cross products a_hi b_lo + a_lo b_hi on the FP64 matrix cores in the same 4-deep
     steps in both tilings: a block of a large product (32 x 32 tiles) equals the same
-    block computed alone (16 x 16 tiles) bit for bit, for every format, also for a depth
-    that is not a multiple of the staging depth, and in the real product."""
+    block computed alone (16 x 16 tiles) bit for bit, for every format, also for depths
+    that are not a multiple of the staging depths (the tilings pad the last 4-deep steps
+    with different numbers of zero steps), and in the real product."""
     import torch
 
     m = n = 720   # 23 x 23 = 529 tiles of 32 x 32: the large-product kernel
